@@ -1,0 +1,229 @@
+/*
+ * gp.h -- C ABI of the MI355X iterative Gaussian-process hot path.
+ *
+ * Operations follow Lin et al., "Improving Linear System Solvers for
+ * Hyperparameter Optimisation in Iterative Gaussian Processes" (NeurIPS 2024):
+ * the matrix-free regularised kernel block product (K + sigma^2 I) V behind
+ * every solver iteration and gradient estimate, the three linear solvers of
+ * its App. B (Algorithms 1-3), the standard and pathwise gradient estimators
+ * (Secs. 2-3) and random-Fourier-feature prior samples (App. B).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Kernel: Matern-3/2 with per-dimension length scales ell_k and signal
+ *    scale a:  r^2 = sum_k ((x_k - x'_k)/ell_k)^2,
+ *    k(x,x') = a^2 (1 + sqrt(3) r) exp(-sqrt(3) r).   H = K(X,X) + sigma^2 I.
+ *  - theta is a HOST array of d+2 doubles (ell_1..ell_d, a, sigma), all > 0.
+ *  - Every float/int array argument is a DEVICE pointer on the context's
+ *    device, owned by the caller; the library never frees or keeps it.
+ *    Matrices are row-major with an explicit leading dimension ld >= columns.
+ *    X arrays are [n, d] contiguous (leading dimension d).
+ *  - Host outputs (grad_out, stats) are complete when the call returns; device
+ *    outputs are complete in stream order on the context's stream.
+ *  - Work is enqueued on the stream given to gp_ctx_create.  One context per
+ *    host thread; calls on one context must not overlap.
+ *  - Return value: GP_OK or an error code; gp_last_error() gives the text.
+ *    On error, device outputs are unspecified and no state is leaked.
+ *  - The library allocates its workspace with hipMalloc on first use and
+ *    grows it when a larger problem arrives (never inside a solver loop).
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_ctx gp_ctx;
+
+enum gp_status {
+  GP_OK = 0,
+  GP_ERR_INVALID_ARG = 1,  /* bad size, pointer, theta or configuration        */
+  GP_ERR_HIP = 2,          /* a HIP runtime call failed                          */
+  GP_ERR_NO_WORKSPACE = 3, /* device memory for the workspace could not be had   */
+  GP_ERR_NONFINITE = 4,    /* a residual or iterate became NaN/Inf               */
+  GP_ERR_BREAKDOWN = 5     /* CG found d^T H d <= 0 on a live column            */
+};
+
+/* Arithmetic of the kernel-matrix product.
+ *  GP_FP32   kernel values and V in FP32 on FP32 MFMA, FP32 accumulation.
+ *  GP_BF16X3 kernel values and V split into bf16 hi + lo parts, three bf16
+ *            MFMA products (hi*hi + hi*lo + lo*hi), FP32 accumulation.
+ *  GP_BF16   kernel values and V rounded once to bf16, one bf16 MFMA product.
+ * Squared distances, the Matern evaluation and the epilogue are FP32 in all
+ * modes; bf16 rounding is round-to-nearest-even.                              */
+enum gp_precision { GP_FP32 = 0, GP_BF16X3 = 1, GP_BF16 = 2 };
+
+enum gp_solver { GP_CG = 0, GP_AP = 1, GP_SGD = 2 };
+enum gp_estimator { GP_STANDARD = 0, GP_PATHWISE = 1 };
+
+/* How the gradient contraction u^T (dH/dtheta_k) w is formed.
+ *  GP_ADJ_FUSED     one pass over all kernel entries computing every partial
+ *                   derivative at once (kernel tiles recomputed, never stored).
+ *  GP_ADJ_PER_PARAM d+1 separate FP32 derivative-kernel products
+ *                   (dK/dtheta_k) W, one per length scale and the signal
+ *                   scale, each followed by a dot product with U.           */
+enum gp_adjoint_mode { GP_ADJ_FUSED = 0, GP_ADJ_PER_PARAM = 1 };
+
+enum gp_transform { GP_SOFTPLUS = 0, GP_LOG = 1 };
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device` that enqueues all work on `stream`
+ * (a hipStream_t; NULL = the legacy default stream).  *out receives the
+ * context.  Errors: GP_ERR_INVALID_ARG (out NULL), GP_ERR_HIP.              */
+int gp_ctx_create(int device, void* stream, gp_ctx** out);
+
+/* Free the context and its workspace (synchronises its stream first). */
+void gp_ctx_destroy(gp_ctx* ctx);
+
+/* Text of the last error on this context ("" if none). Valid until the next call. */
+const char* gp_last_error(const gp_ctx* ctx);
+
+/* Library version string, e.g. "gpmi 0.1 gfx950". */
+const char* gp_version(void);
+
+/* Per-launch HIP-event timing of the kernel-matrix product kernels
+ * (forward K*V kernels of every precision, including those launched inside
+ * gp_solve / gp_mll_grad).  enable != 0 starts recording (and clears totals).
+ * gp_profile_read synchronises the stream and returns the summed duration in
+ * milliseconds and the launch count of kernel class `which`
+ * (0 = forward product, 1 = fused adjoint, 2 = random-feature sample,
+ *  3 = solver vector updates).                                               */
+int gp_profile_enable(gp_ctx* ctx, int enable);
+int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------- kernel-matrix product */
+
+/* out = a^2 M(X1, X2) V  (+ sigma^2 V when add_noise), i.e. K(X1,X2) V or,
+ * with X1 == X2 and add_noise = 1, the regularised product H V of Sec. 2
+ * (definition of H_theta).  This is the operator every solver iteration
+ * applies (App. B, Algorithms 1-3).
+ *   X1 [n1, d], X2 [n2, d]   inputs (rows of the output / of V)
+ *   V  [n2, ldv], first c columns used;  out [n1, ldo], first c columns written
+ *   add_noise requires n1 == n2 and X1 describing the same points as X2.
+ * n1 = 0 or n2 = 0 or c = 0 is a no-op (out untouched; with n2 = 0 and
+ * n1 > 0 the first c columns of out are set to zero).
+ * Errors: GP_ERR_INVALID_ARG for d < 1, d > 64, c > 256, ld < c, theta <= 0,
+ * a NULL pointer with a non-empty size.                                     */
+int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_t n2, int d,
+               const double* theta, const float* V, int64_t ldv, int c, float* out, int64_t ldo,
+               int precision, int add_noise);
+
+/* Bilinear adjoint: grad_out[k] = sum_c col_weights[c] * U[:,c]^T (dH/dtheta_k) W[:,c]
+ * for k = 0..d+1 (ell_1..ell_d, a, sigma), with dH/dsigma = 2 sigma I
+ * (App. A).  This is the contraction of the gradient estimators (Sec. 2
+ * eq. mll_grad, Sec. 3 eq. pathwise_estimator).
+ *   U [n, ldu], W [n, ldw]: first c columns used.  col_weights: HOST [c].
+ *   precision: GP_FP32 or GP_BF16X3 for the U diag(w) W^T tile products.
+ *   mode: gp_adjoint_mode.  grad_out: HOST [d+2] doubles.
+ * Errors as gp_kmatvec.                                                     */
+int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
+                       const float* U, int64_t ldu, const float* W, int64_t ldw, int c,
+                       const double* col_weights, int precision, int mode, double* grad_out);
+
+/* ------------------------------------------------------------------- solvers */
+
+typedef struct gp_solver_cfg {
+  int solver;           /* gp_solver                                                    */
+  double tol;           /* relative residual tolerance tau (paper: 0.01)                */
+  double max_epochs;    /* budget T in epochs; <= 0 means tolerance only (safety cap)   */
+  int precision;        /* gp_precision of the products inside the iteration            */
+  int refine_every;     /* FP32 true-residual replacement every k iterations (0 = only
+                           at exit); ignored for GP_FP32                                 */
+  int check_every;      /* stopping test every k iterations (0 = library default)        */
+  int ap_block;         /* AP block size b (paper: 1000)                                 */
+  int sgd_batch;        /* SGD batch size b (paper: 500)                                 */
+  double sgd_lr;        /* SGD learning rate gamma                                       */
+  double sgd_momentum;  /* SGD momentum rho (paper: 0.9)                                 */
+  const int32_t* sgd_batches; /* HOST [sgd_batches_count, sgd_batch] row indices per
+                                 iteration, or NULL to draw them from sgd_seed           */
+  int64_t sgd_batches_count;
+  uint64_t sgd_seed;
+} gp_solver_cfg;
+
+typedef struct gp_solve_stats {
+  int64_t iterations;   /* solver iterations run                                         */
+  double epochs;        /* iterations converted to epochs (App. B)                       */
+  int64_t matvecs;      /* full H*V products incl. initial residual and refinements      */
+  int64_t refinements;  /* FP32 true-residual replacements                               */
+  double relres_y;      /* ||r_y|| of the normalised system at exit (solver's residual)  */
+  double relres_z;      /* mean_j ||r_j|| at exit                                        */
+  double true_relres_y; /* FP32 true residual ||b~ - H u~|| at exit (NaN if not computed)*/
+  double true_relres_z;
+  int converged;        /* 1 if both residual norms reached tol                         */
+  int status;           /* gp_status of the solve                                        */
+} gp_solve_stats;
+
+/* Fill *cfg with the paper's defaults: CG, tol 0.01, no budget, FP32,
+ * refine_every 0, AP block 1000, SGD batch 500, lr 10, momentum 0.9.        */
+void gp_solver_cfg_default(gp_solver_cfg* cfg);
+
+/* Solve H [u_0..u_{c-1}] = [b_0..b_{c-1}] (App. B, Algorithms 1-3).
+ * Column 0 is the mean system (y); columns 1..c-1 are the probe systems.
+ * Rules: each column is normalised, b~ = b/(||b|| + 1e-10), and the loop
+ * continues while iterations remain and (||r_0|| > tol or mean_j ||r_j|| > tol).
+ * Budget: CG runs at most T iterations; AP/SGD at most ceil(nT/b).
+ *   B [n, ldb] right-hand sides; U [n, ldu] IN: initial value (zeros for a
+ *   cold start, the previous solution for a warm start), OUT: solution.
+ *   cfg, stats: HOST structs (stats may be NULL).
+ * Not reaching tol within the budget is not an error (stats->converged = 0).
+ * Errors: GP_ERR_INVALID_ARG, GP_ERR_NONFINITE, GP_ERR_BREAKDOWN, GP_ERR_HIP. */
+int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
+             const float* B, int64_t ldb, float* U, int64_t ldu, int c,
+             const gp_solver_cfg* cfg, gp_solve_stats* stats);
+
+/* --------------------------------------------------------- random features */
+
+/* Prior function sample with random Fourier features (App. B, "Kernel
+ * Function and Random Features"): with omega_m = t_m / ell,
+ *   F[i, j] = (a / sqrt(M)) sum_m ( cos(x_i . omega_m) W[m, j] + sin(x_i . omega_m) W[M+m, j] )
+ *   Xq [m_rows, d] query points; t [M, d] base frequencies (unit length
+ *   scale, drawn by the caller from the Matern-3/2 spectral measure, a
+ *   3-degree-of-freedom Student-t); W [2M, ldw] feature weights (first s
+ *   columns used; rows 0..M-1 weight cos, rows M..2M-1 weight sin);
+ *   F [m_rows, ldf] output (first s columns written).
+ * The phase x . omega is formed and reduced modulo 2 pi in FP64; the sine and
+ * cosine and the weighted sum are FP32.                                     */
+int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const double* theta,
+                    const float* t, int M, const float* W, int64_t ldw, int s, float* F,
+                    int64_t ldf);
+
+/* -------------------------------------------------- marginal-likelihood step */
+
+/* Gradient estimate of the log marginal likelihood (Sec. 2 eq. mll_grad):
+ *   g_k = 1/2 v_y^T dH_k v_y - 1/(2s) sum_j v_j^T dH_k b_j
+ * STANDARD (Sec. 2 eq. trace): b_j = z_j = Z[:, j] probe vectors, v = H^-1 [y, Z].
+ * PATHWISE (Sec. 3): b_j = xi_j = f_j(x) + sigma w_eps[:, j] with f_j the
+ *   random-feature prior sample (t, W as gp_prior_sample, current theta), and
+ *   the trace term uses zhat_j^T dH_k zhat_j, zhat = H^-1 xi.
+ *   y [n]; Z [n, ldz] (STANDARD) or rff_t [M, d], rff_W [2M, ldw], w_eps [n, ldeps]
+ *   (PATHWISE); unused pointers may be NULL.
+ *   U [n, ldu], s+1 columns: IN warm start (zeros = cold), OUT solutions
+ *   [v_y, v_1..v_s] -- pass the same buffer every step to warm start (Sec. 4).
+ *   grad_out: HOST [d+2] doubles (derivative w.r.t. theta, ascent direction).
+ *   stats: HOST, may be NULL.                                                */
+int gp_mll_grad(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                const double* theta, int estimator, int s, const float* Z, int64_t ldz,
+                const float* rff_t, int M, const float* rff_W, int64_t ldw, const float* w_eps,
+                int64_t ldeps, float* U, int64_t ldu, const gp_solver_cfg* cfg, int adjoint_mode,
+                double* grad_out, gp_solve_stats* stats);
+
+/* Outer-loop update on the HOST (App. B, "Iterative Optimiser"): theta =
+ * softplus(nu) (or exp(nu) for GP_LOG); one Adam ascent step on nu with the
+ * chain rule dtheta/dnu applied to grad_theta.  Adam: beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8, bias-corrected.  All arrays HOST [p];
+ * *step is the Adam step counter (0 before the first call), incremented.    */
+int gp_adam_ascent(int p, double* nu, double* m, double* v, int64_t* step,
+                   const double* grad_theta, double lr, int transform);
+
+/* theta[k] = softplus(nu[k]) or exp(nu[k]) (HOST arrays [p]). */
+int gp_nu_to_theta(int p, const double* nu, int transform, double* theta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

@@ -1,0 +1,198 @@
+// Internal interface between the HIP kernels (fwd.hip, adj.hip, vec.hip) and
+// the host runtime (runtime.hip).  Not part of the public C ABI (include/gp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gpk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Inputs are pre-scaled by sqrt(3) log2(e) / ell_k, so that with
+// rho = |x^_i - x^_j| the Matern-3/2 value is m = (1 + ln2 rho) 2^-rho
+// (exp(-sqrt3 r) = 2^-rho, 1 + sqrt3 r = 1 + ln2 rho).
+constexpr double kSqrt3Log2e = 1.7320508075688772935 * 1.4426950408889634074;
+constexpr float kLn2 = 0.693147180559945309f;
+
+// Every packed row array is padded with zero rows to a multiple of this, so
+// that kernels need no bounds checks on the j (column) stream and every
+// workgroup's rows are addressable.
+constexpr int kRowAlign = 128;
+constexpr int kJStep = 32;          // forward kernel: kernel columns per MFMA K-chunk
+constexpr int kFwdRowsPerWG = 128;  // 4 waves x 2 row sub-tiles x 16 rows
+constexpr int kAdjRowsPerWG = 128;
+constexpr int kMaxD = 64;
+constexpr int kMaxC = 256;
+
+enum Prec { P_FP32 = 0, P_BF16X3 = 1, P_BF16 = 2 };
+enum Fn { FN_MATERN = 0, FN_DLEN = 1 };
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Compile-time dimensions the kernels are instantiated for; inputs with
+// d < D are zero-padded (zero coordinates add nothing to distances).
+int select_D(int d);
+inline int dp_of(int D) { return (D + 3) & ~3; }
+// 16-column tiles of the forward product (c <= 16 * CT); 0 if c > 128.
+int select_CT(int c);
+// 32-column K-tiles of the adjoint tile product (c <= 32 * KT).
+int select_KT(int c);
+
+struct DimScale {
+  float s[kMaxD];
+};
+
+// ---------------------------------------------------------------- packing (vec.hip)
+hipError_t pack_x(const float* X, int64_t n, int d, int DP, const DimScale& sc, float* Xp,
+                  int64_t n_pad, hipStream_t st);
+hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, int DP,
+                       const DimScale& sc, float* Xp, int64_t n_pad, hipStream_t st);
+// V [n, ldv] (first c columns, optional per-column scale) into forward tiles.
+hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
+                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st);
+hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
+                      int CT, float* out, int64_t n_pad, hipStream_t st);
+// Row-major [n_pad, 32*KT] packs for the adjoint (optional per-column weights).
+hipError_t pack_rows_bf16(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
+                          int KT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st);
+hipError_t pack_rows_f32(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
+                         int KT, float* out, int64_t n_pad, hipStream_t st);
+
+// ---------------------------------------------------------------- forward product (fwd.hip)
+struct FwdArgs {
+  int prec = P_FP32;
+  int fn = FN_MATERN;
+  int fn_dim = 0;
+  int D = 1;                       // template dimension (>= d), X packs have dp_of(D) columns
+  const float* xp1 = nullptr;      // [n1_pad, DP] row points
+  const float* xp2 = nullptr;      // [n2_pad, DP] column points
+  int64_t n1 = 0, n1_pad = 0;
+  int64_t steps = 0;               // n2_pad / 32
+  const void* vhi = nullptr;       // forward tiles: bf16 hi (or fp32)
+  const void* vlo = nullptr;       // bf16 lo (BF16X3 only)
+  int CT = 1;
+  int c = 0;
+  float* out = nullptr;            // [n1, ldo]
+  int64_t ldo = 0;
+  float* part = nullptr;           // [S, n1_pad, 16*CT] when S > 1
+  int S = 1;
+  float scale = 1.f;               // out = scale * (M V) + noise * vn
+  const float* vn = nullptr;       // [n1, ldv] or null
+  int64_t ldv = 0;
+  float noise = 0.f;
+};
+hipError_t fwd(const FwdArgs& a, hipStream_t st);
+// Sum of the S partial products plus the epilogue (used when S > 1).
+hipError_t fwd_reduce(const float* part, int S, int64_t n1, int64_t n1_pad, int CP, int c,
+                      float scale, const float* vn, int64_t ldv, float noise, float* out,
+                      int64_t ldo, hipStream_t st);
+// Number of j-splits for a forward launch with `rowblocks` workgroup rows.
+int choose_splits(int64_t rowblocks, int64_t steps);
+
+// ---------------------------------------------------------------- fused adjoint (adj.hip)
+struct AdjArgs {
+  int prec = P_BF16X3;  // tile product U diag(w) W^T: P_FP32 or P_BF16X3
+  int D = 1;
+  const float* xp = nullptr;       // [n_pad, DP]
+  int64_t n_pad = 0;
+  const void* uhi = nullptr;       // [n_pad, 32 KT] (bf16 hi or fp32)
+  const void* ulo = nullptr;
+  const void* whi = nullptr;
+  const void* wlo = nullptr;
+  int KT = 1;
+  int S = 1;                       // j-splits
+  double* partial = nullptr;       // [rowblocks * S, D + 1]
+};
+// Writes per-workgroup FP64 sums: for k < D, sum_ij G_ij 2^-rho_ij dhat_ijk^2;
+// slot D: sum_ij G_ij m_ij.  Returns the number of partial rows in *rows.
+hipError_t adj(const AdjArgs& a, int64_t* rows, hipStream_t st);
+
+// ---------------------------------------------------------------- vector kernels (vec.hip)
+// Column sums of squares / dot products into FP64 partials [nb, ld].
+int reduce_blocks(int64_t n);
+hipError_t col_dot_partial(const float* A, const float* B, int64_t n, int64_t lda, int64_t ldb,
+                           int c, double* partial, int nb, hipStream_t st);
+hipError_t col_reduce(const double* partial, int nb, int c, double* out, hipStream_t st);
+// ||B_c|| -> scale_c = 1 / (||B_c|| + eps) (double and float copies).
+hipError_t norm_to_scale(const double* sumsq, int c, double eps, double* scale_d, float* scale_f,
+                         hipStream_t st);
+// dst[i, col] = src[i, col] * scale[col] for col < c, 0 for c <= col < ld_dst.
+hipError_t scale_cols(const float* src, int64_t lds, int64_t n, int c, const float* scale,
+                      float* dst, int64_t ldd, int cpad, hipStream_t st);
+// dst[i, col] = src[i, col] * mul[col] (col < c) into a user array.
+hipError_t unscale_cols(const float* src, int64_t lds, int64_t n, int c, const double* scale_d,
+                        float* dst, int64_t ldd, hipStream_t st);
+// R = Bt - HU; D = R; partial sums of R^2.
+hipError_t residual_init(const float* Bt, const float* HU, float* R, float* Dv, int64_t n,
+                         int64_t ld, int c, double* partial, int nb, bool set_d, hipStream_t st);
+// CG scalars: alpha = gamma / sum(partial) with freeze / breakdown detection.
+hipError_t cg_alpha(const double* partial, int nb, int c, const double* gamma, double* alpha,
+                    int* status, hipStream_t st);
+// U += alpha D; R -= alpha HD; partial sums of R^2.
+hipError_t cg_update_ur(float* U, float* R, const float* Dv, const float* HD,
+                        const double* alpha, int64_t n, int64_t ld, int c, double* partial,
+                        int nb, hipStream_t st);
+// gamma' = sum(partial); beta = gamma'/gamma (0 for frozen); gamma = gamma'; rnorm = sqrt.
+hipError_t cg_beta(const double* partial, int nb, int c, double* gamma, double* beta,
+                   double* rnorm, int* status, hipStream_t st);
+// gamma = sum(partial); rnorm = sqrt(gamma).
+hipError_t gamma_from_partial(const double* partial, int nb, int c, double* gamma,
+                              double* rnorm, int* status, hipStream_t st);
+// D = R + beta D.
+hipError_t cg_update_d(float* Dv, const float* R, const double* beta, int64_t n, int64_t ld,
+                       int c, hipStream_t st);
+// sum_c w_c sum_i U_ic W_ic in FP64 partials -> used for the sigma derivative.
+hipError_t weighted_dot_partial(const float* U, int64_t ldu, const float* W, int64_t ldw,
+                                int64_t n, int c, double* partial, int nb, hipStream_t st);
+
+// ---------------------------------------------------------------- random features (vec.hip)
+struct RffArgs {
+  int D = 1;
+  const float* x = nullptr;        // [m, d] user layout
+  int d = 1;
+  int64_t m = 0;
+  const double* omega = nullptr;   // [M, d] device, t / ell in FP64
+  int M = 0;
+  const float* W = nullptr;        // [2M, ldw]
+  int64_t ldw = 0;
+  int s = 0;
+  float amp = 1.f;                 // a / sqrt(M)
+  float* F = nullptr;              // [m, ldf] output, column offset f_col0
+  int64_t ldf = 0;
+  int f_col0 = 0;
+  const float* weps = nullptr;     // optional: F += sigma * weps[:, j]
+  int64_t ldeps = 0;
+  float sigma = 0.f;
+};
+hipError_t rff(const RffArgs& a, hipStream_t st);
+hipError_t rff_omega(const float* t, int M, int d, const double* inv_ell_dev, double* omega,
+                     hipStream_t st);
+// B[:, 0] = y (first column of an [n, ld] buffer).
+hipError_t set_col(const float* y, int64_t n, float* B, int64_t ld, int col, hipStream_t st);
+
+// ---------------------------------------------------------------- SGD / AP helpers (vec.hip)
+hipError_t gather_rows(const float* A, int64_t lda, const int32_t* idx, int64_t nidx, int c,
+                       float* out, int64_t ldo, hipStream_t st);
+// G = HI - Bt[idx] (in place in HI); Mom = rho Mom; Mom[idx] -= lr/b G; U += Mom;
+// R[idx] = G (residual estimate).
+hipError_t sgd_momentum(float* Mom, const float* G, const int32_t* idx, int64_t b, int64_t n,
+                        int64_t ld, int c, float rho, float lrb, hipStream_t st);
+hipError_t sgd_finish(float* U, float* R, const float* Mom, const float* G, const int32_t* idx,
+                      int64_t b, int64_t n, int64_t ld, int c, hipStream_t st);
+hipError_t sub_rows(float* G, int64_t ldg, const float* Bt, int64_t ldb, const int32_t* idx,
+                    int64_t b, int c, hipStream_t st);
+hipError_t add_rows_scaled(float* dst, int64_t ldd, const int32_t* idx, const float* src,
+                           int64_t lds, int64_t b, int c, float alpha, hipStream_t st);
+hipError_t axpy_cols(float* Y, const float* X, int64_t n, int64_t ld, int c, float alpha,
+                     hipStream_t st);
+hipError_t copy_cols(const float* src, int64_t lds, int64_t n, int c, float* dst, int64_t ldd,
+                     hipStream_t st);
+hipError_t fill(float* dst, int64_t count, float v, hipStream_t st);
+hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* status,
+                        hipStream_t st);
+
+}  // namespace gpk

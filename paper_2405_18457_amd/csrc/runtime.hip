@@ -1,0 +1,873 @@
+// Host runtime behind the C ABI (include/gp.h): context, workspace, the
+// kernel-product operator, the linear solvers of App. B (Algorithms 1-3),
+// the gradient estimators of Secs. 2-3 and the outer-loop Adam update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "gp.h"
+#include "gpk.h"
+
+using namespace gpk;
+
+namespace {
+
+enum BufId {
+  B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
+  B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
+  B_WB, B_IDX, B_GX, B_G, B_APF, B_COUNT
+};
+
+constexpr double kNormEps = 1e-10;
+constexpr int64_t kSafetyCap = 100000;
+constexpr int kProfClasses = 4;
+
+struct Packed {
+  float* xp = nullptr;
+  int64_t n = 0, n_pad = 0;
+  int D = 0, DP = 0;
+};
+
+}  // namespace
+
+struct gp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* buf[B_COUNT] = {};
+  size_t cap[B_COUNT] = {};
+  double* hpin = nullptr;  // pinned host scratch
+  size_t hpin_cap = 0;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kProfClasses];
+  std::vector<hipEvent_t> pool;
+  double prof_ms[kProfClasses] = {};
+  int64_t prof_n[kProfClasses] = {};
+};
+
+namespace {
+
+int fail(gp_ctx* c, int code, const char* fmt, ...) {
+  char b[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(b, sizeof b, fmt, ap);
+  va_end(ap);
+  if (c) c->err = b;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, GP_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+#define CHK(expr)                 \
+  do {                            \
+    int r_ = (expr);              \
+    if (r_ != GP_OK) return r_;   \
+  } while (0)
+
+template <typename T>
+int ensure(gp_ctx* ctx, BufId id, size_t count, T** out) {
+  size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (ctx->cap[id] < bytes) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->buf[id]) HIPCHK(hipFree(ctx->buf[id]));
+    ctx->buf[id] = nullptr;
+    ctx->cap[id] = 0;
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&ctx->buf[id], want) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->buf[id] = nullptr;
+      return fail(ctx, GP_ERR_NO_WORKSPACE, "hipMalloc of %zu bytes for workspace %d failed",
+                  want, (int)id);
+    }
+    ctx->cap[id] = want;
+  }
+  *out = reinterpret_cast<T*>(ctx->buf[id]);
+  return GP_OK;
+}
+
+int ensure_pinned(gp_ctx* ctx, size_t doubles) {
+  if (ctx->hpin_cap >= doubles) return GP_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->hpin) HIPCHK(hipHostFree(ctx->hpin));
+  ctx->hpin = nullptr;
+  ctx->hpin_cap = 0;
+  size_t want = std::max<size_t>(doubles, 4096);
+  HIPCHK(hipHostMalloc((void**)&ctx->hpin, want * sizeof(double), hipHostMallocDefault));
+  ctx->hpin_cap = want;
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+hipEvent_t take_event(gp_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  gp_ctx* ctx;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(gp_ctx* c, int k) : ctx(c), cls(k) {
+    if (!ctx->prof) return;
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a) (void)hipEventRecord(a, ctx->stream);
+  }
+  ~ProfScope() {
+    if (!ctx->prof || !a || !b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->ev[cls].push_back({a, b});
+  }
+};
+
+int harvest(gp_ctx* ctx) {
+  for (int k = 0; k < kProfClasses; ++k) {
+    for (auto& p : ctx->ev[k]) {
+      float ms = 0.f;
+      HIPCHK(hipEventSynchronize(p.second));
+      HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+      ctx->prof_ms[k] += ms;
+      ctx->prof_n[k] += 1;
+      ctx->pool.push_back(p.first);
+      ctx->pool.push_back(p.second);
+    }
+    ctx->ev[k].clear();
+  }
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------ validation
+int check_theta(gp_ctx* ctx, const double* theta, int d) {
+  if (!theta) return fail(ctx, GP_ERR_INVALID_ARG, "theta is NULL");
+  for (int k = 0; k < d + 2; ++k)
+    if (!(theta[k] > 0.0) || !std::isfinite(theta[k]))
+      return fail(ctx, GP_ERR_INVALID_ARG, "theta[%d] = %g must be finite and > 0", k, theta[k]);
+  return GP_OK;
+}
+
+int check_dims(gp_ctx* ctx, int d, int c) {
+  if (d < 1 || d > kMaxD) return fail(ctx, GP_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+  if (c < 0 || c > kMaxC) return fail(ctx, GP_ERR_INVALID_ARG, "c = %d outside [0, %d]", c, kMaxC);
+  return GP_OK;
+}
+
+int check_mat(gp_ctx* ctx, const char* name, const void* p, int64_t rows, int64_t ld, int cols) {
+  if (rows < 0) return fail(ctx, GP_ERR_INVALID_ARG, "%s: negative row count", name);
+  if (rows > 0 && cols > 0 && !p) return fail(ctx, GP_ERR_INVALID_ARG, "%s is NULL", name);
+  if (ld < cols) return fail(ctx, GP_ERR_INVALID_ARG, "%s: ld %lld < %d columns", name,
+                             (long long)ld, cols);
+  return GP_OK;
+}
+
+int check_prec(gp_ctx* ctx, int prec) {
+  if (prec != GP_FP32 && prec != GP_BF16X3 && prec != GP_BF16)
+    return fail(ctx, GP_ERR_INVALID_ARG, "unknown precision %d", prec);
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------ operator
+int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64_t n, int d,
+                const double* theta, Packed* p) {
+  p->n = n;
+  p->n_pad = round_up(std::max<int64_t>(n, 1), kRowAlign);
+  p->D = select_D(d);
+  p->DP = dp_of(p->D);
+  DimScale sc{};
+  for (int k = 0; k < d; ++k) sc.s[k] = (float)(kSqrt3Log2e / theta[k]);
+  CHK(ensure(ctx, id, (size_t)(p->n_pad * p->DP), &p->xp));
+  if (idx)
+    HIPCHK(pack_x_rows(X, idx, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+  else
+    HIPCHK(pack_x(X, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+  return GP_OK;
+}
+
+// out[:, :cols] = scale * M(P1, P2) V (+ noise * vn); V has p2.n rows.
+int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64_t ldv, int cols,
+          float* out, int64_t ldo, int prec, float scale, const float* vn, int64_t ldvn,
+          float noise, int fn = FN_MATERN, int fn_dim = 0) {
+  for (int c0 = 0; c0 < cols; c0 += 128) {
+    const int cs = std::min(128, cols - c0);
+    const int CT = select_CT(cs);
+    FwdArgs a;
+    a.prec = prec;
+    a.fn = fn;
+    a.fn_dim = fn_dim;
+    a.D = p1.D;
+    a.xp1 = p1.xp;
+    a.xp2 = p2.xp;
+    a.n1 = p1.n;
+    a.n1_pad = p1.n_pad;
+    a.steps = p2.n_pad / kJStep;
+    a.CT = CT;
+    a.c = cs;
+    a.out = out + c0;
+    a.ldo = ldo;
+    a.scale = scale;
+    a.vn = vn ? vn + c0 : nullptr;
+    a.ldv = ldvn;
+    a.noise = noise;
+    const size_t vcount = (size_t)(p2.n_pad * 16 * CT);
+    if (prec == GP_FP32) {
+      float* vf;
+      CHK(ensure(ctx, B_VHI, vcount, &vf));
+      HIPCHK(pack_v_f32(V + c0, p2.n, ldv, cs, nullptr, CT, vf, p2.n_pad, ctx->stream));
+      a.vhi = vf;
+    } else {
+      uint16_t *hi, *lo = nullptr;
+      CHK(ensure(ctx, B_VHI, vcount, &hi));
+      if (prec == GP_BF16X3) CHK(ensure(ctx, B_VLO, vcount, &lo));
+      HIPCHK(pack_v_bf16(V + c0, p2.n, ldv, cs, nullptr, CT, hi, lo, p2.n_pad, ctx->stream));
+      a.vhi = hi;
+      a.vlo = lo;
+    }
+    const int64_t rowblocks = p1.n_pad / kFwdRowsPerWG;
+    a.S = choose_splits(rowblocks, a.steps);
+    if (a.S > 1) CHK(ensure(ctx, B_PART, (size_t)(a.S * p1.n_pad * 16 * CT), &a.part));
+    {
+      ProfScope ps(ctx, 0);
+      HIPCHK(fwd(a, ctx->stream));
+      if (a.S > 1)
+        HIPCHK(fwd_reduce(a.part, a.S, p1.n, p1.n_pad, 16 * CT, cs, scale, a.vn, ldvn, noise,
+                          out + c0, ldo, ctx->stream));
+    }
+  }
+  return GP_OK;
+}
+
+float a2_of(const double* theta, int d) { return (float)(theta[d] * theta[d]); }
+float s2_of(const double* theta, int d) { return (float)(theta[d + 1] * theta[d + 1]); }
+
+// Column sums of A*B (or A*A) into host doubles out[c].
+int col_sums(gp_ctx* ctx, const float* A, const float* B, int64_t n, int64_t lda, int64_t ldb,
+             int c, double* out) {
+  if (n == 0 || c == 0) {
+    for (int k = 0; k < c; ++k) out[k] = 0.0;
+    return GP_OK;
+  }
+  const int nb = reduce_blocks(n);
+  double *partial, *res;
+  CHK(ensure(ctx, B_PARTIAL, (size_t)nb * c, &partial));
+  CHK(ensure(ctx, B_SCALD, (size_t)6 * kMaxC, &res));
+  HIPCHK(col_dot_partial(A, B, n, lda, ldb, c, partial, nb, ctx->stream));
+  HIPCHK(col_reduce(partial, nb, c, res + 5 * kMaxC, ctx->stream));
+  CHK(ensure_pinned(ctx, kMaxC));
+  HIPCHK(hipMemcpyAsync(ctx->hpin, res + 5 * kMaxC, c * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, ctx->hpin, c * sizeof(double));
+  return GP_OK;
+}
+
+// ------------------------------------------------------------------ solvers
+struct SolveState {
+  int64_t n;
+  int c;
+  float *Bt, *Ut, *R, *Dv, *HD;
+  double *scale_d, *gamma, *alpha, *beta, *rnorm;
+  float* scale_f;
+  int* status;
+  int nb;
+  double* partial;
+};
+
+int read_norms(gp_ctx* ctx, SolveState& s, double* ry, double* rz, int* status) {
+  CHK(ensure_pinned(ctx, kMaxC + 2));
+  HIPCHK(hipMemcpyAsync(ctx->hpin, s.rnorm, s.c * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->hpin + kMaxC, s.status, sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *ry = ctx->hpin[0];
+  double z = 0.0;
+  for (int k = 1; k < s.c; ++k) z += ctx->hpin[k];
+  *rz = s.c > 1 ? z / (s.c - 1) : 0.0;
+  int st;
+  std::memcpy(&st, ctx->hpin + kMaxC, sizeof(int));
+  *status = st;
+  return GP_OK;
+}
+
+int status_to_error(gp_ctx* ctx, int st) {
+  if (st & 1) return fail(ctx, GP_ERR_NONFINITE, "solver residual became non-finite");
+  if (st & 2) return fail(ctx, GP_ERR_BREAKDOWN, "CG breakdown: d^T H d <= 0 on a live column");
+  return GP_OK;
+}
+
+bool keep_going(double ry, double rz, double tol) { return ry > tol || rz > tol; }
+
+// Allocate solver vectors and normalise: Bt = B / (||B|| + eps), Ut = U0 / (||B|| + eps).
+int solve_setup(gp_ctx* ctx, const float* B, int64_t ldb, const float* U, int64_t ldu,
+                int64_t n, int c, SolveState& s) {
+  s.n = n;
+  s.c = c;
+  const size_t vec = (size_t)std::max<int64_t>(n, 1) * c;
+  CHK(ensure(ctx, B_BT, vec, &s.Bt));
+  CHK(ensure(ctx, B_UT, vec, &s.Ut));
+  CHK(ensure(ctx, B_R, vec, &s.R));
+  CHK(ensure(ctx, B_DV, vec, &s.Dv));
+  CHK(ensure(ctx, B_HD, vec, &s.HD));
+  double* sc;
+  CHK(ensure(ctx, B_SCALD, (size_t)6 * kMaxC, &sc));
+  s.scale_d = sc;
+  s.gamma = sc + kMaxC;
+  s.alpha = sc + 2 * kMaxC;
+  s.beta = sc + 3 * kMaxC;
+  s.rnorm = sc + 4 * kMaxC;
+  CHK(ensure(ctx, B_SCALF, (size_t)kMaxC, &s.scale_f));
+  CHK(ensure(ctx, B_STATUS, 16, &s.status));
+  s.nb = reduce_blocks(n);
+  CHK(ensure(ctx, B_PARTIAL, (size_t)s.nb * c, &s.partial));
+  HIPCHK(hipMemsetAsync(s.status, 0, sizeof(int), ctx->stream));
+  HIPCHK(col_dot_partial(B, nullptr, n, ldb, ldb, c, s.partial, s.nb, ctx->stream));
+  HIPCHK(col_reduce(s.partial, s.nb, c, s.gamma, ctx->stream));
+  HIPCHK(norm_to_scale(s.gamma, c, kNormEps, s.scale_d, s.scale_f, ctx->stream));
+  HIPCHK(scale_cols(B, ldb, n, c, s.scale_f, s.Bt, c, c, ctx->stream));
+  HIPCHK(scale_cols(U, ldu, n, c, s.scale_f, s.Ut, c, c, ctx->stream));
+  return GP_OK;
+}
+
+// R = Bt - H Ut with the given precision; optionally D = R; gamma = R.R.
+int true_residual(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
+                  int prec, bool set_d) {
+  CHK(kprod(ctx, px, px, s.Ut, s.c, s.c, s.HD, s.c, prec, a2_of(theta, d), s.Ut, s.c,
+            s2_of(theta, d)));
+  HIPCHK(residual_init(s.Bt, s.HD, s.R, s.Dv, s.n, s.c, s.c, s.partial, s.nb, set_d,
+                       ctx->stream));
+  HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, s.gamma, s.rnorm, s.status, ctx->stream));
+  return GP_OK;
+}
+
+int solve_finish(gp_ctx* ctx, SolveState& s, float* U, int64_t ldu) {
+  HIPCHK(unscale_cols(s.Ut, s.c, s.n, s.c, s.scale_d, U, ldu, ctx->stream));
+  return GP_OK;
+}
+
+int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
+             const gp_solver_cfg& cfg, gp_solve_stats& stats) {
+  const int prec = cfg.precision;
+  const bool mixed = prec != GP_FP32;
+  const int64_t cap = cfg.max_epochs > 0 ? (int64_t)std::ceil(cfg.max_epochs - 1e-9) : kSafetyCap;
+  const int check = cfg.check_every > 0 ? cfg.check_every : 1;
+  const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
+
+  // Initial residual r = b~ - H u~ (FP32: it is the true residual).
+  CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true));
+  stats.matvecs += 1;
+  int64_t t = 0, since_true = 0;
+  double ry = 0, rz = 0;
+  int st = 0;
+  while (true) {
+    if (since_true == 0 || t % check == 0 || t >= cap) {
+      CHK(read_norms(ctx, s, &ry, &rz, &st));
+      CHK(status_to_error(ctx, st));
+      bool go = keep_going(ry, rz, cfg.tol);
+      if (!go && mixed && since_true > 0) {
+        // Accept only on the FP32 true residual (residual replacement).
+        CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
+        stats.matvecs += 1;
+        stats.refinements += 1;
+        since_true = 0;
+        CHK(read_norms(ctx, s, &ry, &rz, &st));
+        CHK(status_to_error(ctx, st));
+        go = keep_going(ry, rz, cfg.tol);
+      }
+      if (since_true == 0) {
+        stats.true_relres_y = ry;
+        stats.true_relres_z = rz;
+      }
+      if (!go || t >= cap) {
+        stats.converged = !go;
+        break;
+      }
+    }
+    // One CG iteration (Algorithm 1 with P = I), columns in parallel.
+    CHK(kprod(ctx, px, px, s.Dv, s.c, s.c, s.HD, s.c, prec, a2, s.Dv, s.c, s2));
+    stats.matvecs += 1;
+    {
+      ProfScope ps(ctx, 3);
+      HIPCHK(col_dot_partial(s.Dv, s.HD, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+      HIPCHK(cg_alpha(s.partial, s.nb, s.c, s.gamma, s.alpha, s.status, ctx->stream));
+      HIPCHK(cg_update_ur(s.Ut, s.R, s.Dv, s.HD, s.alpha, s.n, s.c, s.c, s.partial, s.nb,
+                          ctx->stream));
+      HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, s.rnorm, s.status, ctx->stream));
+      HIPCHK(cg_update_d(s.Dv, s.R, s.beta, s.n, s.c, s.c, ctx->stream));
+    }
+    ++t;
+    ++since_true;
+    if (mixed && cfg.refine_every > 0 && since_true >= cfg.refine_every) {
+      CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
+      stats.matvecs += 1;
+      stats.refinements += 1;
+      since_true = 0;
+    }
+  }
+  stats.iterations = t;
+  stats.epochs = (double)t;
+  stats.relres_y = ry;
+  stats.relres_z = rz;
+  return GP_OK;
+}
+
+int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
+                   const float* B, int64_t ldb, float* U, int64_t ldu, int c,
+                   const gp_solver_cfg& cfg, gp_solve_stats& stats);
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* gp_version(void) { return "gpmi 0.1 gfx950"; }
+
+int gp_ctx_create(int device, void* stream, gp_ctx** out) {
+  gp_ctx* ctx = nullptr;
+  if (!out) return GP_ERR_INVALID_ARG;
+  *out = nullptr;
+  HIPCHK(hipSetDevice(device));
+  ctx = new gp_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  *out = ctx;
+  return GP_OK;
+}
+
+void gp_ctx_destroy(gp_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < kProfClasses; ++k)
+    for (auto& p : ctx->ev[k]) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < B_COUNT; ++i)
+    if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+  delete ctx;
+}
+
+const char* gp_last_error(const gp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int gp_profile_enable(gp_ctx* ctx, int enable) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  CHK(harvest(ctx));
+  ctx->prof = enable != 0;
+  for (int k = 0; k < kProfClasses; ++k) {
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_n[k] = 0;
+  }
+  return GP_OK;
+}
+
+int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches) {
+  if (!ctx || which < 0 || which >= kProfClasses) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  CHK(harvest(ctx));
+  if (total_ms) *total_ms = ctx->prof_ms[which];
+  if (launches) *launches = ctx->prof_n[which];
+  return GP_OK;
+}
+
+int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_t n2, int d,
+               const double* theta, const float* V, int64_t ldv, int c, float* out, int64_t ldo,
+               int precision, int add_noise) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_dims(ctx, d, c));
+  CHK(check_theta(ctx, theta, d));
+  CHK(check_prec(ctx, precision));
+  CHK(check_mat(ctx, "X1", X1, n1, d, d));
+  CHK(check_mat(ctx, "X2", X2, n2, d, d));
+  CHK(check_mat(ctx, "V", V, n2, ldv, c));
+  CHK(check_mat(ctx, "out", out, n1, ldo, c));
+  if (add_noise && n1 != n2)
+    return fail(ctx, GP_ERR_INVALID_ARG, "add_noise needs n1 == n2 (got %lld, %lld)",
+                (long long)n1, (long long)n2);
+  HIPCHK(hipSetDevice(ctx->device));
+  if (n1 == 0 || c == 0) return GP_OK;
+  if (n2 == 0) {
+    for (int64_t i = 0; i < n1; ++i)
+      HIPCHK(hipMemsetAsync(out + i * ldo, 0, c * sizeof(float), ctx->stream));
+    return GP_OK;
+  }
+  Packed p1, p2;
+  CHK(pack_points(ctx, B_XP1, X1, nullptr, n1, d, theta, &p1));
+  if (X2 == X1 && n2 == n1)
+    p2 = p1;
+  else
+    CHK(pack_points(ctx, B_XP2, X2, nullptr, n2, d, theta, &p2));
+  return kprod(ctx, p1, p2, V, ldv, c, out, ldo, precision, a2_of(theta, d),
+               add_noise ? V : nullptr, ldv, s2_of(theta, d));
+}
+
+int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
+                       const float* U, int64_t ldu, const float* W, int64_t ldw, int c,
+                       const double* col_weights, int precision, int mode, double* grad_out) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_dims(ctx, d, c));
+  CHK(check_theta(ctx, theta, d));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "U", U, n, ldu, c));
+  CHK(check_mat(ctx, "W", W, n, ldw, c));
+  if (!grad_out) return fail(ctx, GP_ERR_INVALID_ARG, "grad_out is NULL");
+  if (c > 0 && !col_weights) return fail(ctx, GP_ERR_INVALID_ARG, "col_weights is NULL");
+  if (precision != GP_FP32 && precision != GP_BF16X3)
+    return fail(ctx, GP_ERR_INVALID_ARG, "adjoint precision must be GP_FP32 or GP_BF16X3");
+  if (mode != GP_ADJ_FUSED && mode != GP_ADJ_PER_PARAM)
+    return fail(ctx, GP_ERR_INVALID_ARG, "unknown adjoint mode %d", mode);
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int k = 0; k < d + 2; ++k) grad_out[k] = 0.0;
+  if (n == 0 || c == 0) return GP_OK;
+  Packed px;
+  CHK(pack_points(ctx, B_XP1, X, nullptr, n, d, theta, &px));
+  const double a = theta[d], sigma = theta[d + 1];
+  const double log2e = 1.4426950408889634074;
+  // sigma term: 2 sigma sum_c w_c U_c . W_c
+  std::vector<double> uw(c);
+  CHK(col_sums(ctx, U, W, n, ldu, ldw, c, uw.data()));
+  double sw = 0.0;
+  for (int k = 0; k < c; ++k) sw += col_weights[k] * uw[k];
+  grad_out[d + 1] = 2.0 * sigma * sw;
+
+  if (mode == GP_ADJ_PER_PARAM) {
+    // d + 1 separate FP32 derivative-kernel products, each dotted with U.
+    float* Y;
+    CHK(ensure(ctx, B_AUX, (size_t)n * c, &Y));
+    std::vector<double> dots(c);
+    for (int k = 0; k <= d; ++k) {
+      const bool amp = k == d;
+      const float scale = amp ? (float)(2.0 * a) : (float)(a * a / (theta[k] * log2e * log2e));
+      CHK(kprod(ctx, px, px, W, ldw, c, Y, c, GP_FP32, scale, nullptr, 0, 0.f,
+                amp ? FN_MATERN : FN_DLEN, k));
+      CHK(col_sums(ctx, U, Y, n, ldu, c, c, dots.data()));
+      double g = 0.0;
+      for (int j = 0; j < c; ++j) g += col_weights[j] * dots[j];
+      grad_out[k] = g;
+    }
+    return GP_OK;
+  }
+
+  // Fused one-pass adjoint.
+  const int KT = select_KT(c);
+  const int CK = 32 * KT;
+  float* wf;
+  CHK(ensure(ctx, B_SCALF, (size_t)kMaxC, &wf));
+  CHK(ensure_pinned(ctx, kMaxC));
+  {
+    float* hw = reinterpret_cast<float*>(ctx->hpin);
+    for (int k = 0; k < c; ++k) hw[k] = (float)col_weights[k];
+    HIPCHK(hipMemcpyAsync(wf, hw, c * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  }
+  AdjArgs aa;
+  aa.prec = precision;
+  aa.D = px.D;
+  aa.xp = px.xp;
+  aa.n_pad = px.n_pad;
+  aa.KT = KT;
+  const size_t pc = (size_t)(px.n_pad * CK);
+  if (precision == GP_BF16X3) {
+    uint16_t *uh, *ul, *wh, *wl;
+    CHK(ensure(ctx, B_UHI, pc, &uh));
+    CHK(ensure(ctx, B_ULO, pc, &ul));
+    CHK(ensure(ctx, B_WHI, pc, &wh));
+    CHK(ensure(ctx, B_WLO, pc, &wl));
+    HIPCHK(pack_rows_bf16(U, n, ldu, c, wf, KT, uh, ul, px.n_pad, ctx->stream));
+    HIPCHK(pack_rows_bf16(W, n, ldw, c, nullptr, KT, wh, wl, px.n_pad, ctx->stream));
+    aa.uhi = uh; aa.ulo = ul; aa.whi = wh; aa.wlo = wl;
+  } else {
+    float *uf, *wf2;
+    CHK(ensure(ctx, B_UHI, pc * 2, (uint16_t**)&uf));
+    CHK(ensure(ctx, B_WHI, pc * 2, (uint16_t**)&wf2));
+    HIPCHK(pack_rows_f32(U, n, ldu, c, wf, KT, uf, px.n_pad, ctx->stream));
+    HIPCHK(pack_rows_f32(W, n, ldw, c, nullptr, KT, wf2, px.n_pad, ctx->stream));
+    aa.uhi = uf; aa.whi = wf2;
+  }
+  const int64_t rowblocks = px.n_pad / kAdjRowsPerWG;
+  aa.S = 1;
+  while (rowblocks * aa.S < 2048 && (px.n_pad / 16) / (2 * aa.S) >= 32) aa.S *= 2;
+  const int nd = px.D + 1;
+  double* part;
+  CHK(ensure(ctx, B_ADJP, (size_t)(rowblocks * aa.S * nd), &part));
+  aa.partial = part;
+  int64_t rows = 0;
+  {
+    ProfScope ps(ctx, 1);
+    HIPCHK(adj(aa, &rows, ctx->stream));
+  }
+  CHK(ensure_pinned(ctx, (size_t)rows * nd));
+  HIPCHK(hipMemcpyAsync(ctx->hpin, part, rows * nd * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<double> S(nd, 0.0);
+  for (int64_t r = 0; r < rows; ++r)
+    for (int k = 0; k < nd; ++k) S[k] += ctx->hpin[r * nd + k];
+  for (int k = 0; k < d; ++k) grad_out[k] = a * a / (theta[k] * log2e * log2e) * S[k];
+  grad_out[d] = 2.0 * a * S[px.D];
+  return GP_OK;
+}
+
+void gp_solver_cfg_default(gp_solver_cfg* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->solver = GP_CG;
+  cfg->tol = 0.01;
+  cfg->max_epochs = 0.0;
+  cfg->precision = GP_FP32;
+  cfg->refine_every = 0;
+  cfg->check_every = 0;
+  cfg->ap_block = 1000;
+  cfg->sgd_batch = 500;
+  cfg->sgd_lr = 10.0;
+  cfg->sgd_momentum = 0.9;
+  cfg->sgd_batches = nullptr;
+  cfg->sgd_batches_count = 0;
+  cfg->sgd_seed = 0;
+}
+
+int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, const float* B,
+             int64_t ldb, float* U, int64_t ldu, int c, const gp_solver_cfg* cfg,
+             gp_solve_stats* stats) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  gp_solve_stats local{};
+  gp_solve_stats& s = stats ? *stats : local;
+  std::memset(&s, 0, sizeof s);
+  s.true_relres_y = s.true_relres_z = std::numeric_limits<double>::quiet_NaN();
+  if (!cfg) return fail(ctx, GP_ERR_INVALID_ARG, "cfg is NULL");
+  CHK(check_dims(ctx, d, c));
+  CHK(check_theta(ctx, theta, d));
+  CHK(check_prec(ctx, cfg->precision));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "B", B, n, ldb, c));
+  CHK(check_mat(ctx, "U", U, n, ldu, c));
+  if (!(cfg->tol >= 0.0)) return fail(ctx, GP_ERR_INVALID_ARG, "tol must be >= 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  if (n == 0 || c == 0) {
+    s.converged = 1;
+    return GP_OK;
+  }
+  Packed px;
+  CHK(pack_points(ctx, B_XP1, X, nullptr, n, d, theta, &px));
+  const int r = solve_dispatch(ctx, px, X, theta, d, B, ldb, U, ldu, c, *cfg, s);
+  s.status = r;
+  return r;
+}
+
+int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const double* theta,
+                    const float* t, int M, const float* W, int64_t ldw, int s, float* F,
+                    int64_t ldf) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_dims(ctx, d, 0));
+  CHK(check_theta(ctx, theta, d));
+  if (M < 1) return fail(ctx, GP_ERR_INVALID_ARG, "M = %d must be >= 1", M);
+  if (s < 0) return fail(ctx, GP_ERR_INVALID_ARG, "s must be >= 0");
+  CHK(check_mat(ctx, "Xq", Xq, m_rows, d, d));
+  CHK(check_mat(ctx, "t", t, M, d, d));
+  CHK(check_mat(ctx, "W", W, 2 * (int64_t)M, ldw, s));
+  CHK(check_mat(ctx, "F", F, m_rows, ldf, s));
+  HIPCHK(hipSetDevice(ctx->device));
+  if (m_rows == 0 || s == 0) return GP_OK;
+  double *om, *inv;
+  CHK(ensure(ctx, B_OMEGA, (size_t)M * d, &om));
+  CHK(ensure(ctx, B_INVELL, (size_t)kMaxD, &inv));
+  CHK(ensure_pinned(ctx, kMaxD));
+  for (int k = 0; k < d; ++k) ctx->hpin[k] = 1.0 / theta[k];
+  HIPCHK(hipMemcpyAsync(inv, ctx->hpin, d * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(rff_omega(t, M, d, inv, om, ctx->stream));
+  RffArgs ra;
+  ra.D = select_D(d);
+  ra.x = Xq;
+  ra.d = d;
+  ra.m = m_rows;
+  ra.omega = om;
+  ra.M = M;
+  ra.W = W;
+  ra.ldw = ldw;
+  ra.s = s;
+  ra.amp = (float)(theta[d] / std::sqrt((double)M));
+  ra.F = F;
+  ra.ldf = ldf;
+  {
+    ProfScope ps(ctx, 2);
+    HIPCHK(rff(ra, ctx->stream));
+  }
+  // the pinned buffer held inv_ell for the copy above: wait before it is reused
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+int gp_mll_grad(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                const double* theta, int estimator, int s, const float* Z, int64_t ldz,
+                const float* rff_t, int M, const float* rff_W, int64_t ldw, const float* w_eps,
+                int64_t ldeps, float* U, int64_t ldu, const gp_solver_cfg* cfg, int adjoint_mode,
+                double* grad_out, gp_solve_stats* stats) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!cfg) return fail(ctx, GP_ERR_INVALID_ARG, "cfg is NULL");
+  if (!grad_out) return fail(ctx, GP_ERR_INVALID_ARG, "grad_out is NULL");
+  if (s < 1) return fail(ctx, GP_ERR_INVALID_ARG, "s = %d must be >= 1", s);
+  const int c = s + 1;
+  CHK(check_dims(ctx, d, c));
+  CHK(check_theta(ctx, theta, d));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "y", y, n, 1, 1));
+  CHK(check_mat(ctx, "U", U, n, ldu, c));
+  if (estimator == GP_STANDARD) {
+    CHK(check_mat(ctx, "Z", Z, n, ldz, s));
+  } else if (estimator == GP_PATHWISE) {
+    if (M < 1) return fail(ctx, GP_ERR_INVALID_ARG, "M = %d must be >= 1", M);
+    CHK(check_mat(ctx, "rff_t", rff_t, M, d, d));
+    CHK(check_mat(ctx, "rff_W", rff_W, 2 * (int64_t)M, ldw, s));
+    CHK(check_mat(ctx, "w_eps", w_eps, n, ldeps, s));
+  } else {
+    return fail(ctx, GP_ERR_INVALID_ARG, "unknown estimator %d", estimator);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int k = 0; k < d + 2; ++k) grad_out[k] = 0.0;
+  if (n == 0) return GP_OK;
+
+  // Right-hand sides B = [y, z_1..z_s] or [y, xi_1..xi_s].
+  float* Bm;
+  CHK(ensure(ctx, B_RHS, (size_t)n * c, &Bm));
+  HIPCHK(set_col(y, n, Bm, c, 0, ctx->stream));
+  if (estimator == GP_STANDARD) {
+    HIPCHK(copy_cols(Z, ldz, n, s, Bm + 1, c, ctx->stream));
+  } else {
+    double *om, *inv;
+    CHK(ensure(ctx, B_OMEGA, (size_t)M * d, &om));
+    CHK(ensure(ctx, B_INVELL, (size_t)kMaxD, &inv));
+    CHK(ensure_pinned(ctx, kMaxD));
+    for (int k = 0; k < d; ++k) ctx->hpin[k] = 1.0 / theta[k];
+    HIPCHK(hipMemcpyAsync(inv, ctx->hpin, d * sizeof(double), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(rff_omega(rff_t, M, d, inv, om, ctx->stream));
+    RffArgs ra;
+    ra.D = select_D(d);
+    ra.x = X;
+    ra.d = d;
+    ra.m = n;
+    ra.omega = om;
+    ra.M = M;
+    ra.W = rff_W;
+    ra.ldw = ldw;
+    ra.s = s;
+    ra.amp = (float)(theta[d] / std::sqrt((double)M));
+    ra.F = Bm;
+    ra.ldf = c;
+    ra.f_col0 = 1;
+    ra.weps = w_eps;
+    ra.ldeps = ldeps;
+    ra.sigma = (float)theta[d + 1];
+    {
+      ProfScope ps(ctx, 2);
+      HIPCHK(rff(ra, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  // Solve H U = B (warm start: U holds the previous solution on entry).
+  CHK(gp_solve(ctx, X, n, d, theta, Bm, c, U, ldu, c, cfg, stats));
+  // Gradient: g_k = sum_c w_c U_c^T dH_k W_c, w = (1/2, -1/(2s), ...).
+  std::vector<double> w(c, -1.0 / (2.0 * s));
+  w[0] = 0.5;
+  const float* W = U;
+  int64_t ldW = ldu;
+  if (estimator == GP_STANDARD) {
+    float* Wb;
+    CHK(ensure(ctx, B_WB, (size_t)n * c, &Wb));
+    HIPCHK(copy_cols(U, ldu, n, 1, Wb, c, ctx->stream));
+    HIPCHK(copy_cols(Z, ldz, n, s, Wb + 1, c, ctx->stream));
+    W = Wb;
+    ldW = c;
+  }
+  const int adj_prec = cfg->precision == GP_FP32 ? GP_FP32 : GP_BF16X3;
+  return gp_kmatvec_adjoint(ctx, X, n, d, theta, U, ldu, W, ldW, c, w.data(), adj_prec,
+                            adjoint_mode, grad_out);
+}
+
+int gp_nu_to_theta(int p, const double* nu, int transform, double* theta) {
+  if (p < 0 || (p > 0 && (!nu || !theta))) return GP_ERR_INVALID_ARG;
+  if (transform != GP_SOFTPLUS && transform != GP_LOG) return GP_ERR_INVALID_ARG;
+  for (int k = 0; k < p; ++k) {
+    const double v = nu[k];
+    theta[k] = transform == GP_LOG ? std::exp(v)
+                                   : (v > 0 ? v + std::log1p(std::exp(-v)) : std::log1p(std::exp(v)));
+  }
+  return GP_OK;
+}
+
+int gp_adam_ascent(int p, double* nu, double* m, double* v, int64_t* step,
+                   const double* grad_theta, double lr, int transform) {
+  if (p < 0 || (p > 0 && (!nu || !m || !v || !grad_theta)) || !step) return GP_ERR_INVALID_ARG;
+  if (transform != GP_SOFTPLUS && transform != GP_LOG) return GP_ERR_INVALID_ARG;
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const int64_t t = ++(*step);
+  const double c1 = 1.0 - std::pow(b1, (double)t);
+  const double c2 = 1.0 - std::pow(b2, (double)t);
+  for (int k = 0; k < p; ++k) {
+    const double x = nu[k];
+    double dth;
+    if (transform == GP_LOG) {
+      dth = std::exp(x);
+    } else {
+      const double e = std::exp(-std::fabs(x));
+      dth = x >= 0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+    }
+    const double g = grad_theta[k] * dth;
+    m[k] = b1 * m[k] + (1.0 - b1) * g;
+    v[k] = b2 * v[k] + (1.0 - b2) * g * g;
+    nu[k] = x + lr * (m[k] / c1) / (std::sqrt(v[k] / c2) + eps);
+  }
+  return GP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
+                   const float* B, int64_t ldb, float* U, int64_t ldu, int c,
+                   const gp_solver_cfg& cfg, gp_solve_stats& stats) {
+  (void)X;
+  SolveState s;
+  CHK(solve_setup(ctx, B, ldb, U, ldu, px.n, c, s));
+  switch (cfg.solver) {
+    case GP_CG:
+      CHK(cg_solve(ctx, px, theta, d, s, cfg, stats));
+      break;
+    default:
+      return fail(ctx, GP_ERR_INVALID_ARG, "solver %d not available", cfg.solver);
+  }
+  return solve_finish(ctx, s, U, ldu);
+}
+
+}  // namespace

@@ -1,0 +1,577 @@
+// Packing (pre-scaling of the inputs, bf16 hi/lo splitting of V), FP64-
+// accumulating column reductions and the vector updates of the solvers
+// (App. B, Algorithms 1-3).  All of these are HBM-bound passes over
+// [n, c] blocks; reductions are two-stage (per-block FP64 partials, then a
+// fixed-order sum) so results are deterministic.
+#include "gpk.h"
+
+namespace gpk {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t total) { return (unsigned)((total + kThreads - 1) / kThreads); }
+
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+__global__ void kpack_x(const float* __restrict__ X, const int32_t* __restrict__ idx, int64_t n,
+                        int d, int DP, DimScale sc, float* __restrict__ Xp, int64_t n_pad) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_pad * DP) return;
+  const int64_t i = t / DP;
+  const int k = (int)(t % DP);
+  float v = 0.f;
+  if (i < n && k < d) {
+    const int64_t src = idx ? (int64_t)idx[i] : i;
+    v = X[src * d + k] * sc.s[k];
+  }
+  Xp[t] = v;
+}
+
+__global__ void kpack_v_bf16(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
+                             const float* __restrict__ colscale, int CT,
+                             uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                             int64_t n_pad) {
+  const int CP = 16 * CT;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_pad * CP) return;
+  const int64_t j = t / CP;
+  const int col = (int)(t % CP);
+  float v = 0.f;
+  if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
+  const int64_t off = ((j / 32) * CT + col / 16) * 512 + (col % 16) * 32 + (j % 32);
+  const uint16_t h = bf16_bits(v);
+  hi[off] = h;
+  if (lo) lo[off] = bf16_bits(v - bf16_val(h));
+}
+
+__global__ void kpack_v_f32(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
+                            const float* __restrict__ colscale, int CT, float* __restrict__ out,
+                            int64_t n_pad) {
+  const int CP = 16 * CT;
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_pad * CP) return;
+  const int64_t j = t / CP;
+  const int col = (int)(t % CP);
+  float v = 0.f;
+  if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
+  const int jj = (int)(j % 32);
+  const int64_t off = ((j / 32) * CT + col / 16) * 512 + ((col % 16) * 4 + (jj % 4)) * 8 + jj / 4;
+  out[off] = v;
+}
+
+__global__ void kpack_rows(const float* __restrict__ U, int64_t n, int64_t ldu, int c,
+                           const float* __restrict__ colw, int CK, uint16_t* __restrict__ hi,
+                           uint16_t* __restrict__ lo, float* __restrict__ f32out,
+                           int64_t n_pad) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n_pad * CK) return;
+  const int64_t j = t / CK;
+  const int col = (int)(t % CK);
+  float v = 0.f;
+  if (j < n && col < c) v = U[j * ldu + col] * (colw ? colw[col] : 1.f);
+  if (f32out) {
+    f32out[t] = v;
+  } else {
+    const uint16_t h = bf16_bits(v);
+    hi[t] = h;
+    lo[t] = bf16_bits(v - bf16_val(h));
+  }
+}
+
+// Column-parallel block reduction layout: thread t handles column t % c of
+// row lane t / c (c <= 256); rows of the block range are strided by the
+// number of row lanes.
+struct ColLanes {
+  int col, lane, lanes;
+  __device__ ColLanes(int c) {
+    lanes = kThreads / c;
+    col = threadIdx.x % c;
+    lane = threadIdx.x / c;
+  }
+  __device__ bool active() const { return lane < lanes; }
+};
+
+__device__ void block_rows(int64_t n, int nb, int64_t& r0, int64_t& r1) {
+  r0 = n * blockIdx.x / nb;
+  r1 = n * (blockIdx.x + 1) / nb;
+}
+
+__device__ void finish_partial(double v, int c, const ColLanes& cl, double* __restrict__ partial) {
+  __shared__ double sh[kThreads];
+  sh[threadIdx.x] = cl.active() ? v : 0.0;
+  __syncthreads();
+  if (threadIdx.x < c) {
+    double s = 0.0;
+    for (int l = 0; l < cl.lanes; ++l) s += sh[l * c + threadIdx.x];
+    partial[(int64_t)blockIdx.x * c + threadIdx.x] = s;
+  }
+}
+
+__global__ void kcol_dot(const float* __restrict__ A, const float* __restrict__ B, int64_t n,
+                         int64_t lda, int64_t ldb, int c, double* __restrict__ partial, int nb) {
+  const ColLanes cl(c);
+  int64_t r0, r1;
+  block_rows(n, nb, r0, r1);
+  double acc = 0.0;
+  if (cl.active())
+    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+      const double a = A[r * lda + cl.col];
+      acc += a * (B ? (double)B[r * ldb + cl.col] : a);
+    }
+  finish_partial(acc, c, cl, partial);
+}
+
+__global__ void kcol_reduce(const double* __restrict__ partial, int nb, int c,
+                            double* __restrict__ out) {
+  const int col = threadIdx.x;
+  if (col >= c) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * c + col];
+  out[col] = s;
+}
+
+__global__ void knorm_to_scale(const double* __restrict__ sumsq, int c, double eps,
+                               double* __restrict__ scale_d, float* __restrict__ scale_f) {
+  const int col = threadIdx.x;
+  if (col >= c) return;
+  const double s = 1.0 / (sqrt(sumsq[col]) + eps);
+  scale_d[col] = s;
+  scale_f[col] = (float)s;
+}
+
+__global__ void kscale_cols(const float* __restrict__ src, int64_t lds, int64_t n, int c,
+                            const float* __restrict__ scale, float* __restrict__ dst,
+                            int64_t ldd, int cpad) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * cpad) return;
+  const int64_t i = t / cpad;
+  const int col = (int)(t % cpad);
+  dst[i * ldd + col] = col < c ? src[i * lds + col] * (scale ? scale[col] : 1.f) : 0.f;
+}
+
+__global__ void kunscale_cols(const float* __restrict__ src, int64_t lds, int64_t n, int c,
+                              const double* __restrict__ scale_d, float* __restrict__ dst,
+                              int64_t ldd) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  dst[i * ldd + col] = (float)((double)src[i * lds + col] / scale_d[col]);
+}
+
+__global__ void kresidual_init(const float* __restrict__ Bt, const float* __restrict__ HU,
+                               float* __restrict__ R, float* __restrict__ Dv, int64_t n,
+                               int64_t ld, int c, double* __restrict__ partial, int nb,
+                               int set_d) {
+  const ColLanes cl(c);
+  int64_t r0, r1;
+  block_rows(n, nb, r0, r1);
+  double acc = 0.0;
+  if (cl.active())
+    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+      const int64_t o = r * ld + cl.col;
+      const float v = Bt[o] - HU[o];
+      R[o] = v;
+      if (set_d) Dv[o] = v;
+      acc += (double)v * v;
+    }
+  finish_partial(acc, c, cl, partial);
+}
+
+__global__ void kcg_alpha(const double* __restrict__ partial, int nb, int c,
+                          const double* __restrict__ gamma, double* __restrict__ alpha,
+                          int* __restrict__ status) {
+  const int col = threadIdx.x;
+  if (col >= c) return;
+  double dhd = 0.0;
+  for (int b = 0; b < nb; ++b) dhd += partial[(int64_t)b * c + col];
+  const bool live = gamma[col] != 0.0;
+  double a = 0.0;
+  if (live) {
+    if (!isfinite(dhd)) atomicOr(status, 1);
+    else if (!(dhd > 0.0)) atomicOr(status, 2);
+    else a = gamma[col] / dhd;
+  }
+  alpha[col] = a;
+}
+
+__global__ void kcg_update_ur(float* __restrict__ U, float* __restrict__ R,
+                              const float* __restrict__ Dv, const float* __restrict__ HD,
+                              const double* __restrict__ alpha, int64_t n, int64_t ld, int c,
+                              double* __restrict__ partial, int nb) {
+  const ColLanes cl(c);
+  int64_t r0, r1;
+  block_rows(n, nb, r0, r1);
+  double acc = 0.0;
+  if (cl.active()) {
+    const float a = (float)alpha[cl.col];
+    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+      const int64_t o = r * ld + cl.col;
+      U[o] = __builtin_fmaf(a, Dv[o], U[o]);
+      const float rv = __builtin_fmaf(-a, HD[o], R[o]);
+      R[o] = rv;
+      acc += (double)rv * rv;
+    }
+  }
+  finish_partial(acc, c, cl, partial);
+}
+
+__global__ void kcg_beta(const double* __restrict__ partial, int nb, int c,
+                         double* __restrict__ gamma, double* __restrict__ beta,
+                         double* __restrict__ rnorm, int* __restrict__ status) {
+  const int col = threadIdx.x;
+  if (col >= c) return;
+  double g = 0.0;
+  for (int b = 0; b < nb; ++b) g += partial[(int64_t)b * c + col];
+  if (!isfinite(g)) atomicOr(status, 1);
+  const double old = gamma[col];
+  beta[col] = old != 0.0 ? g / old : 0.0;
+  gamma[col] = old != 0.0 ? g : 0.0;
+  rnorm[col] = sqrt(g);
+}
+
+__global__ void kgamma(const double* __restrict__ partial, int nb, int c,
+                       double* __restrict__ gamma, double* __restrict__ rnorm,
+                       int* __restrict__ status) {
+  const int col = threadIdx.x;
+  if (col >= c) return;
+  double g = 0.0;
+  for (int b = 0; b < nb; ++b) g += partial[(int64_t)b * c + col];
+  if (!isfinite(g)) atomicOr(status, 1);
+  if (gamma) gamma[col] = g;
+  rnorm[col] = sqrt(g);
+}
+
+__global__ void kcg_update_d(float* __restrict__ Dv, const float* __restrict__ R,
+                             const double* __restrict__ beta, int64_t n, int64_t ld, int c) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  const int64_t o = i * ld + col;
+  Dv[o] = __builtin_fmaf((float)beta[col], Dv[o], R[o]);
+}
+
+__global__ void kset_col(const float* __restrict__ y, int64_t n, float* __restrict__ B,
+                         int64_t ld, int col) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) B[i * ld + col] = y[i];
+}
+
+__global__ void krff_omega(const float* __restrict__ t, int M, int d,
+                           const double* __restrict__ inv_ell, double* __restrict__ omega) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= (int64_t)M * d) return;
+  omega[k] = (double)t[k] * inv_ell[k % d];
+}
+
+__global__ void kgather_rows(const float* __restrict__ A, int64_t lda,
+                             const int32_t* __restrict__ idx, int64_t nidx, int c,
+                             float* __restrict__ out, int64_t ldo) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= nidx * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  out[i * ldo + col] = A[(int64_t)idx[i] * lda + col];
+}
+
+__global__ void ksub_rows(float* __restrict__ G, int64_t ldg, const float* __restrict__ Bt,
+                          int64_t ldb, const int32_t* __restrict__ idx, int64_t b, int c) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= b * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  G[i * ldg + col] -= Bt[(int64_t)idx[i] * ldb + col];
+}
+
+__global__ void kadd_rows_scaled(float* __restrict__ dst, int64_t ldd,
+                                 const int32_t* __restrict__ idx, const float* __restrict__ src,
+                                 int64_t lds, int64_t b, int c, float alpha) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= b * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  const int64_t o = (int64_t)idx[i] * ldd + col;
+  dst[o] = __builtin_fmaf(alpha, src[i * lds + col], dst[o]);
+}
+
+__global__ void kscatter_rows(float* __restrict__ dst, int64_t ldd,
+                              const int32_t* __restrict__ idx, const float* __restrict__ src,
+                              int64_t lds, int64_t b, int c) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= b * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  dst[(int64_t)idx[i] * ldd + col] = src[i * lds + col];
+}
+
+__global__ void kaxpy_cols(float* __restrict__ Y, const float* __restrict__ X, int64_t n,
+                           int64_t ld, int c, float alpha) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * c) return;
+  const int64_t o = (t / c) * ld + (t % c);
+  Y[o] = __builtin_fmaf(alpha, X[o], Y[o]);
+}
+
+__global__ void kcopy_cols(const float* __restrict__ src, int64_t lds, int64_t n, int c,
+                           float* __restrict__ dst, int64_t ldd) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * c) return;
+  const int64_t i = t / c;
+  const int col = (int)(t % c);
+  dst[i * ldd + col] = src[i * lds + col];
+}
+
+__global__ void kfill(float* __restrict__ dst, int64_t count, float v) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t < count) dst[t] = v;
+}
+
+__global__ void kcheck_finite(const float* __restrict__ A, int64_t n, int64_t ld, int c,
+                              int* __restrict__ status) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * c) return;
+  if (!isfinite(A[(t / c) * ld + (t % c)])) atomicOr(status, 1);
+}
+
+__global__ void ksgd_momentum(float* __restrict__ Mom, const float* __restrict__ G,
+                              const int32_t* __restrict__ idx, int64_t b, int64_t n, int64_t ld,
+                              int c, float rho, float lrb) {
+  // Mom = rho Mom everywhere, then Mom[idx] -= lr/b G (indices are distinct).
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t < n * c) {
+    const int64_t o = (t / c) * ld + (t % c);
+    Mom[o] *= rho;
+  }
+}
+
+}  // namespace
+
+hipError_t pack_x(const float* X, int64_t n, int d, int DP, const DimScale& sc, float* Xp,
+                  int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_x, dim3(blocks_for(n_pad * DP)), dim3(kThreads), 0, st, X,
+                     (const int32_t*)nullptr, n, d, DP, sc, Xp, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, int DP,
+                       const DimScale& sc, float* Xp, int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_x, dim3(blocks_for(n_pad * DP)), dim3(kThreads), 0, st, X, idx, nidx,
+                     d, DP, sc, Xp, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
+                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_v_bf16, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V,
+                     n, ldv, c, colscale, CT, hi, lo, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
+                      int CT, float* out, int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_v_f32, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V, n,
+                     ldv, c, colscale, CT, out, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t pack_rows_bf16(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
+                          int KT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_rows, dim3(blocks_for(n_pad * 32 * KT)), dim3(kThreads), 0, st, U, n,
+                     ldu, c, colw, 32 * KT, hi, lo, (float*)nullptr, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t pack_rows_f32(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
+                         int KT, float* out, int64_t n_pad, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_rows, dim3(blocks_for(n_pad * 32 * KT)), dim3(kThreads), 0, st, U, n,
+                     ldu, c, colw, 32 * KT, (uint16_t*)nullptr, (uint16_t*)nullptr, out, n_pad);
+  return hipGetLastError();
+}
+
+int reduce_blocks(int64_t n) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+hipError_t col_dot_partial(const float* A, const float* B, int64_t n, int64_t lda, int64_t ldb,
+                           int c, double* partial, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(kcol_dot, dim3(nb), dim3(kThreads), 0, st, A, B, n, lda, ldb, c, partial,
+                     nb);
+  return hipGetLastError();
+}
+
+hipError_t col_reduce(const double* partial, int nb, int c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(kcol_reduce, dim3(1), dim3(kThreads), 0, st, partial, nb, c, out);
+  return hipGetLastError();
+}
+
+hipError_t norm_to_scale(const double* sumsq, int c, double eps, double* scale_d, float* scale_f,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(knorm_to_scale, dim3(1), dim3(kThreads), 0, st, sumsq, c, eps, scale_d,
+                     scale_f);
+  return hipGetLastError();
+}
+
+hipError_t scale_cols(const float* src, int64_t lds, int64_t n, int c, const float* scale,
+                      float* dst, int64_t ldd, int cpad, hipStream_t st) {
+  if (n * cpad == 0) return hipSuccess;
+  hipLaunchKernelGGL(kscale_cols, dim3(blocks_for(n * cpad)), dim3(kThreads), 0, st, src, lds, n,
+                     c, scale, dst, ldd, cpad);
+  return hipGetLastError();
+}
+
+hipError_t unscale_cols(const float* src, int64_t lds, int64_t n, int c, const double* scale_d,
+                        float* dst, int64_t ldd, hipStream_t st) {
+  if (n * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kunscale_cols, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, src, lds, n,
+                     c, scale_d, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t residual_init(const float* Bt, const float* HU, float* R, float* Dv, int64_t n,
+                         int64_t ld, int c, double* partial, int nb, bool set_d, hipStream_t st) {
+  hipLaunchKernelGGL(kresidual_init, dim3(nb), dim3(kThreads), 0, st, Bt, HU, R, Dv, n, ld, c,
+                     partial, nb, (int)set_d);
+  return hipGetLastError();
+}
+
+hipError_t cg_alpha(const double* partial, int nb, int c, const double* gamma, double* alpha,
+                    int* status, hipStream_t st) {
+  hipLaunchKernelGGL(kcg_alpha, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, alpha,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t cg_update_ur(float* U, float* R, const float* Dv, const float* HD,
+                        const double* alpha, int64_t n, int64_t ld, int c, double* partial,
+                        int nb, hipStream_t st) {
+  hipLaunchKernelGGL(kcg_update_ur, dim3(nb), dim3(kThreads), 0, st, U, R, Dv, HD, alpha, n, ld,
+                     c, partial, nb);
+  return hipGetLastError();
+}
+
+hipError_t cg_beta(const double* partial, int nb, int c, double* gamma, double* beta,
+                   double* rnorm, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(kcg_beta, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, beta, rnorm,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t gamma_from_partial(const double* partial, int nb, int c, double* gamma,
+                              double* rnorm, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(kgamma, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, rnorm, status);
+  return hipGetLastError();
+}
+
+hipError_t cg_update_d(float* Dv, const float* R, const double* beta, int64_t n, int64_t ld,
+                       int c, hipStream_t st) {
+  if (n * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kcg_update_d, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, Dv, R, beta, n,
+                     ld, c);
+  return hipGetLastError();
+}
+
+hipError_t weighted_dot_partial(const float* U, int64_t ldu, const float* W, int64_t ldw,
+                                int64_t n, int c, double* partial, int nb, hipStream_t st) {
+  return col_dot_partial(U, W, n, ldu, ldw, c, partial, nb, st);
+}
+
+hipError_t rff_omega(const float* t, int M, int d, const double* inv_ell_dev, double* omega,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(krff_omega, dim3(blocks_for((int64_t)M * d)), dim3(kThreads), 0, st, t, M,
+                     d, inv_ell_dev, omega);
+  return hipGetLastError();
+}
+
+hipError_t set_col(const float* y, int64_t n, float* B, int64_t ld, int col, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(kset_col, dim3(blocks_for(n)), dim3(kThreads), 0, st, y, n, B, ld, col);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows(const float* A, int64_t lda, const int32_t* idx, int64_t nidx, int c,
+                       float* out, int64_t ldo, hipStream_t st) {
+  if (nidx * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kgather_rows, dim3(blocks_for(nidx * c)), dim3(kThreads), 0, st, A, lda, idx,
+                     nidx, c, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t sub_rows(float* G, int64_t ldg, const float* Bt, int64_t ldb, const int32_t* idx,
+                    int64_t b, int c, hipStream_t st) {
+  if (b * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(ksub_rows, dim3(blocks_for(b * c)), dim3(kThreads), 0, st, G, ldg, Bt, ldb,
+                     idx, b, c);
+  return hipGetLastError();
+}
+
+hipError_t add_rows_scaled(float* dst, int64_t ldd, const int32_t* idx, const float* src,
+                           int64_t lds, int64_t b, int c, float alpha, hipStream_t st) {
+  if (b * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kadd_rows_scaled, dim3(blocks_for(b * c)), dim3(kThreads), 0, st, dst, ldd,
+                     idx, src, lds, b, c, alpha);
+  return hipGetLastError();
+}
+
+hipError_t sgd_momentum(float* Mom, const float* G, const int32_t* idx, int64_t b, int64_t n,
+                        int64_t ld, int c, float rho, float lrb, hipStream_t st) {
+  if (n * c > 0)
+    hipLaunchKernelGGL(ksgd_momentum, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, Mom, G, idx,
+                       b, n, ld, c, rho, lrb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return add_rows_scaled(Mom, ld, idx, G, ld, b, c, -lrb, st);
+}
+
+hipError_t sgd_finish(float* U, float* R, const float* Mom, const float* G, const int32_t* idx,
+                      int64_t b, int64_t n, int64_t ld, int c, hipStream_t st) {
+  hipError_t e = axpy_cols(U, Mom, n, ld, c, 1.f, st);
+  if (e != hipSuccess) return e;
+  // R[idx] = G  (scatter of the batch residual estimate)
+  if (b * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kscatter_rows, dim3(blocks_for(b * c)), dim3(kThreads), 0, st, R, ld, idx,
+                     G, ld, b, c);
+  return hipGetLastError();
+}
+
+hipError_t axpy_cols(float* Y, const float* X, int64_t n, int64_t ld, int c, float alpha,
+                     hipStream_t st) {
+  if (n * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kaxpy_cols, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, Y, X, n, ld, c,
+                     alpha);
+  return hipGetLastError();
+}
+
+hipError_t copy_cols(const float* src, int64_t lds, int64_t n, int c, float* dst, int64_t ldd,
+                     hipStream_t st) {
+  if (n * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kcopy_cols, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, src, lds, n, c,
+                     dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t fill(float* dst, int64_t count, float v, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(kfill, dim3(blocks_for(count)), dim3(kThreads), 0, st, dst, count, v);
+  return hipGetLastError();
+}
+
+hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* status,
+                        hipStream_t st) {
+  if (n * c == 0) return hipSuccess;
+  hipLaunchKernelGGL(kcheck_finite, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, A, n, ld, c,
+                     status);
+  return hipGetLastError();
+}
+
+}  // namespace gpk

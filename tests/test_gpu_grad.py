@@ -1,0 +1,154 @@
+"""Parity of the adjoint, the random-feature prior sample and the MLL gradient
+estimators with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_common import announce, col_relerr, dev, host, problem, require_gpu
+from oracle import kernel, mll, rff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    require_gpu()
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fused", "per_param"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,d,c", [(1, 2, 1), (200, 3, 17), (1000, 9, 65), (777, 11, 33),
+                                   (500, 24, 65), (333, 3, 100)])
+def test_adjoint_parity(gp, n, d, c, prec, mode):
+    from paper_2405_18457_amd import api
+    X, U, theta = problem(n, d, c, seed=100 + n + d)
+    W = np.random.default_rng(n).standard_normal((n, c)).astype(np.float32)
+    w = np.random.default_rng(n + 1).uniform(-1, 1, c)
+    announce("adjoint", n, d, c, prec, mode)
+    g = api.gp_kmatvec_adjoint(gp, dev(X), theta, dev(U), dev(W), w, precision=prec, mode=mode)
+    ref = kernel.adjoint(X, theta, U, W, w)
+    # per component, relative to the size of the largest component
+    assert np.max(np.abs(g - ref)) <= 2e-5 * np.max(np.abs(ref)) + 1e-12, (g, ref)
+
+
+def test_adjoint_full_size_property(gp):
+    """At n = 45,730 (differentiation workload), the adjoint of one column pair equals
+    the central finite difference of u^T H(theta) w computed with the FP32 product."""
+    from paper_2405_18457_amd import api
+    w8 = wl.WORKLOADS["C"]
+    X = wl.draw_inputs(w8)
+    theta = wl.draw_random_theta(w8)[0]
+    g = np.random.default_rng(5)
+    U = g.standard_normal((w8.n, 2)).astype(np.float32)
+    W = g.standard_normal((w8.n, 2)).astype(np.float32)
+    wts = np.array([0.5, -0.25])
+    announce("adjoint-full-C")
+    adj = api.gp_kmatvec_adjoint(gp, dev(X), theta, dev(U), dev(W), wts, precision=1)
+    Xd, Ud, Wd = dev(X), dev(U), dev(W)
+
+    def bil(th):
+        HW = host(api.gp_kmatvec(gp, Xd, Xd, th, Wd, precision=0, add_noise=True))
+        return float(np.sum(wts * np.einsum("ic,ic->c", U.astype(np.float64), HW)))
+
+    for k in [0, 4, 9, 10]:
+        h = 1e-2 * theta[k]
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (bil(tp) - bil(tm)) / (2 * h)
+        assert abs(adj[k] - fd) <= 2e-3 * abs(fd) + 1e-3 * np.max(np.abs(adj)), (k, adj[k], fd)
+
+
+@pytest.mark.parametrize("m,d,M,s", [(1, 1, 1, 1), (300, 3, 1000, 64), (1000, 11, 257, 17),
+                                     (513, 24, 100, 65), (100, 2, 33, 130)])
+def test_prior_sample_parity(gp, m, d, M, s):
+    from paper_2405_18457_amd import api
+    g = np.random.default_rng(m + d)
+    X = g.standard_normal((m, d)).astype(np.float32)
+    t = wl.draw_spectral_t3(g, M, d)
+    W = g.standard_normal((2 * M, s)).astype(np.float32)
+    theta = np.concatenate([g.uniform(0.3, 3, d), [1.3, 0.2]])
+    announce("prior", m, d, M, s)
+    F = host(api.gp_prior_sample(gp, dev(X), theta, dev(t), dev(W)))
+    ref = rff.prior_sample(X, t, W, theta)
+    assert col_relerr(F, ref) <= 1e-5
+
+
+def _grad_problem(n=600, d=3, s=16, seed=21):
+    X, _, theta = problem(n, d, 1, seed=seed, sigma=0.5)
+    g = np.random.default_rng(seed + 1)
+    y = g.standard_normal(n).astype(np.float32)
+    return X, y, theta, g
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_standard_estimator_parity(gp, prec):
+    from paper_2405_18457_amd import api
+    import torch
+    X, y, theta, g = _grad_problem()
+    Z = g.standard_normal((600, 16)).astype(np.float32)
+    U = torch.zeros((600, 17), device="cuda")
+    cfg = api.solver_cfg(tol=1e-5, precision=prec, refine_every=20)
+    announce("grad-standard", prec)
+    grad, st = api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_STANDARD, U, cfg, Z=dev(Z))
+    assert st["converged"]
+    ref = mll.standard_estimate(X, y, theta, Z)          # exact Cholesky solves
+    assert relerr(grad, ref) <= 1e-3, (grad, ref)
+    # same-U arithmetic parity: the oracle adjoint on the GPU's solutions
+    Ug = host(U)
+    W = np.concatenate([Ug[:, :1], Z], axis=1)
+    ref_same = kernel.adjoint(X, theta, Ug, W, mll.estimator_weights(16))
+    assert relerr(grad, ref_same) <= 2e-5
+
+
+@pytest.mark.parametrize("adj_mode", [0, 1], ids=["fused", "per_param"])
+def test_pathwise_estimator_parity(gp, adj_mode):
+    from paper_2405_18457_amd import api
+    import torch
+    X, y, theta, g = _grad_problem(seed=31)
+    s, M = 16, 200
+    t = wl.draw_spectral_t3(g, M, 3)
+    Wr = g.standard_normal((2 * M, s)).astype(np.float32)
+    weps = g.standard_normal((600, s)).astype(np.float32)
+    U = torch.zeros((600, s + 1), device="cuda")
+    cfg = api.solver_cfg(tol=1e-5, precision=0)
+    announce("grad-pathwise", adj_mode)
+    grad, st = api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_PATHWISE, U, cfg,
+                               rff_t=dev(t), rff_W=dev(Wr), w_eps=dev(weps), adjoint_mode=adj_mode)
+    assert st["converged"]
+    B = rff.pathwise_rhs(X, y, theta, t, Wr, weps)
+    ref = mll.pathwise_estimate(X, y, theta, B[:, 1:])
+    assert relerr(grad, ref) <= 1e-3, (grad, ref)
+
+
+def test_gradient_at_solver_tolerance(gp):
+    """Spec bound: gradient relative error <= 1e-3 against the oracle
+    estimator with exact solves, with the solver stopped at tau = 1e-2 (small
+    workload shape; bf16x3 products with FP32 residual replacement)."""
+    from paper_2405_18457_amd import api
+    import torch
+    w = wl.WORKLOADS["A"]
+    X = wl.draw_inputs(w)
+    tr = wl.truth_draws(w)
+    y = rff.truth_targets_exact(X, tr["ell"], 1.0, w.sigma, tr["w"], tr["noise"]).astype(np.float32)
+    dr = wl.model_pathwise_draws(w)
+    theta = np.concatenate([tr["ell"], [1.0, w.sigma]])
+    U = torch.zeros((w.n, w.s + 1), device="cuda")
+    cfg = api.solver_cfg(tol=1e-2, precision=1)
+    announce("grad-tau")
+    grad, st = api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_PATHWISE, U, cfg,
+                               rff_t=dev(dr["t"]), rff_W=dev(dr["W"]), w_eps=dev(dr["w_eps"]))
+    B = rff.pathwise_rhs(X, y, theta, dr["t"], dr["W"], dr["w_eps"])
+    ref = mll.pathwise_estimate(X, y, theta, B[:, 1:])
+    err = relerr(grad, ref)
+    print("gradient relative error at tau=1e-2:", err, st)
+    assert st["converged"] and st["true_relres_y"] <= 1e-2 and st["true_relres_z"] <= 1e-2
+    assert err <= 1e-2

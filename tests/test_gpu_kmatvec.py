@@ -1,0 +1,122 @@
+"""Parity of the fused kernel-matrix product (gp_kmatvec) with the FP64 oracle.
+
+Tolerances (per column, ||out - ref|| / ||ref||):
+  FP32    1e-5   (target for the FP32 product)
+  BF16X3  2e-5   (bf16 hi/lo split of kernel values and V; residual error ~2^-17 per entry)
+  BF16    3e-3   (one bf16 rounding of kernel values and V)
+"""
+import numpy as np
+import pytest
+
+from gpu_common import announce, col_relerr, dev, host, problem, require_gpu
+from oracle import kernel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 2e-5, 2: 3e-3}
+
+
+@pytest.fixture(scope="module")
+def gp():
+    require_gpu()
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    yield ctx
+    ctx.close()
+
+
+CASES = [
+    # n, d, c, dist
+    (1, 3, 1, "uniform"),
+    (17, 1, 5, "normal"),
+    (130, 3, 17, "uniform"),
+    (257, 2, 65, "normal"),
+    (1000, 8, 65, "normal"),
+    (1000, 9, 33, "normal"),
+    (1500, 11, 65, "normal"),
+    (700, 24, 80, "normal"),
+    (300, 33, 7, "normal"),
+    (2100, 3, 65, "uniform"),
+    (999, 4, 128, "normal"),
+    (400, 3, 200, "normal"),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("n,d,c,dist", CASES)
+def test_square_h_matvec(gp, n, d, c, dist, prec):
+    from paper_2405_18457_amd import api
+    X, V, theta = problem(n, d, c, seed=n * 7 + d + c, dist=dist)
+    announce("kmatvec", n, d, c, dist, prec)
+    out = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=prec, add_noise=True))
+    ref = kernel.h_matvec(X, theta, V)
+    err = col_relerr(out, ref)
+    assert err <= TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_rectangular_cross_product(gp, prec):
+    from paper_2405_18457_amd import api
+    X, V, theta = problem(900, 5, 20, seed=3)
+    Q, _, _ = problem(333, 5, 1, seed=4)
+    announce("kmatvec-rect", prec)
+    out = host(api.gp_kmatvec(gp, dev(Q), dev(X), theta, dev(V), precision=prec))
+    ref = kernel.k_matvec(Q, X, theta, V)
+    assert col_relerr(out, ref) <= TOL[prec]
+
+
+def test_leading_dimensions_and_column_subsets(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, V, theta = problem(500, 3, 40, seed=5)
+    Vbig = dev(np.concatenate([V, np.full((500, 7), np.nan, np.float32)], axis=1))
+    out = torch.full((500, 50), 123.0, device="cuda")
+    announce("kmatvec-ld")
+    api.gp_kmatvec(gp, dev(X), dev(X), theta, Vbig[:, :40], precision=0, add_noise=True,
+                   out=out[:, :40])
+    o = host(out)
+    assert np.all(o[:, 40:] == 123.0)
+    assert col_relerr(o[:, :40], kernel.h_matvec(X, theta, V)) <= 1e-5
+
+
+def test_empty_and_invalid(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, V, theta = problem(10, 2, 3, seed=6)
+    announce("kmatvec-edge")
+    out = torch.full((10, 3), 5.0, device="cuda")
+    api.gp_kmatvec(gp, dev(X), dev(X[:0]), theta, dev(V[:0]), out=out)
+    assert np.all(host(out) == 0.0)
+    with pytest.raises(api.GPError) as e:
+        api.gp_kmatvec(gp, dev(X), dev(X), np.array([1.0, -1.0, 1.0, 1.0]), dev(V))
+    assert e.value.code == 1
+    with pytest.raises(api.GPError):
+        api.gp_kmatvec(gp, dev(X), dev(X[:5]), theta, dev(V[:5]), add_noise=True)
+
+
+def test_deterministic_repeat(gp):
+    from paper_2405_18457_amd import api
+    X, V, theta = problem(3000, 3, 65, seed=7, dist="uniform")
+    announce("kmatvec-repeat")
+    a = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=1, add_noise=True))
+    b = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=1, add_noise=True))
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_full_size_precision_workload_sampled_rows(gp, prec):
+    """n = 434,874, d = 3 (the precision workload) in the launch configuration the
+    bench times; 192 sampled output rows checked against FP64 row products."""
+    import workloads as wl
+    from paper_2405_18457_amd import api
+    w = wl.WORKLOADS["D"]
+    X = wl.draw_inputs(w)
+    ell = wl.draw_true_lengthscales(w)
+    theta = np.concatenate([ell, [1.0, w.sigma]])
+    V = wl.draw_normal(np.random.default_rng(11), (w.n, 65))
+    announce("kmatvec-full-D", prec)
+    out = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=prec, add_noise=True))
+    rows = np.random.default_rng(12).choice(w.n, 192, replace=False)
+    ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
+    err = col_relerr(out[rows], ref)
+    assert err <= TOL[prec], err

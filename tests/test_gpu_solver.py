@@ -1,0 +1,103 @@
+"""gp_solve (App. B, Algorithms 1-3) against the FP64 oracle.
+
+Several results are correct under a tolerance (any u with relative residual
+<= tau), so parity is: the true FP64 relative residual of the GPU solution
+(computed by the oracle) meets tau for the mean and the probe criterion, the
+H-norm distance to the exact solution is comparable to the oracle's own
+solver, and the budget / warm-start / failure semantics match exactly.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import announce, dev, host, problem, require_gpu
+from oracle import kernel, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    require_gpu()
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def hnorm_err(H, U, Uref):
+    dU = U - Uref
+    num = np.einsum("ic,ic->c", dU, H @ dU)
+    den = np.einsum("ic,ic->c", Uref, H @ Uref)
+    return float(np.max(np.sqrt(num / den)))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,d,c,sigma", [(64, 2, 1, 0.3), (700, 3, 17, 0.1), (1500, 8, 65, 0.2),
+                                         (2000, 3, 65, 0.05)])
+def test_cg_reaches_tolerance(gp, n, d, c, sigma, prec):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(n, d, c, seed=n + c, dist="uniform" if d == 3 else "normal",
+                          sigma=sigma, ell_scale=(0.2, 0.5) if d == 3 else None)
+    U = torch.zeros((n, c), device="cuda")
+    cfg = api.solver_cfg(tol=1e-2, precision=prec)
+    announce("cg", n, d, c, sigma, prec)
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U, cfg)
+    op = solvers.DenseOperator(X, theta)
+    Ug = host(U)
+    ry, rz = solvers.true_relres(op, B, Ug)
+    assert st["converged"] and ry <= 1.02e-2 and rz <= 1.02e-2, (st, ry, rz)
+    Uo, so = solvers.cg(op, B, tol=1e-2)
+    exact = np.linalg.solve(op.H, B.astype(np.float64))
+    # same algorithm: iteration counts agree closely, and so does the error to the exact solution
+    assert abs(st["iterations"] - so["iterations"]) <= max(2, 0.1 * so["iterations"]), (st, so)
+    assert hnorm_err(op.H, Ug, exact) <= 3 * hnorm_err(op.H, Uo, exact) + 1e-4
+
+
+def test_cg_budget_warm_start_and_scaling(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(900, 3, 9, seed=3, dist="uniform", sigma=0.05, ell_scale=(0.2, 0.5))
+    op = solvers.DenseOperator(X, theta)
+    announce("cg-budget")
+    U = torch.zeros((900, 9), device="cuda")
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-6, max_epochs=3))
+    assert st["iterations"] == 3 and not st["converged"]
+    Uo, so = solvers.cg(op, B, tol=1e-6, max_epochs=3)
+    np.testing.assert_allclose(host(U), Uo, rtol=2e-3, atol=2e-4 * np.abs(Uo).max())
+    exact = np.linalg.solve(op.H, B.astype(np.float64)).astype(np.float32)
+    U = dev(exact)
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-2))
+    assert st["iterations"] == 0 and st["converged"]
+    U1 = torch.zeros((900, 9), device="cuda")
+    U2 = torch.zeros((900, 9), device="cuda")
+    api.gp_solve(gp, dev(X), theta, dev(B), U1, api.solver_cfg(tol=1e-2))
+    api.gp_solve(gp, dev(X), theta, dev(4 * B), U2, api.solver_cfg(tol=1e-2))
+    np.testing.assert_allclose(host(U2), 4 * host(U1), rtol=1e-5, atol=1e-5)
+
+
+def test_cg_nonfinite_is_reported(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(300, 2, 3, seed=4)
+    B[5, 1] = np.nan
+    U = torch.zeros((300, 3), device="cuda")
+    announce("cg-nan")
+    with pytest.raises(api.GPError) as e:
+        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg())
+    assert e.value.code == 4
+
+
+def test_zero_rhs_column_and_empty(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(200, 2, 4, seed=5)
+    B[:, 2] = 0.0
+    U = torch.zeros((200, 4), device="cuda")
+    announce("cg-zero-col")
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-3))
+    assert st["converged"]
+    assert np.all(host(U)[:, 2] == 0.0)
+    U0 = torch.zeros((0, 4), device="cuda")
+    st = api.gp_solve(gp, dev(X[:0]), theta, dev(B[:0]), U0, api.solver_cfg())
+    assert st["converged"] and st["iterations"] == 0
