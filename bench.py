@@ -1,0 +1,224 @@
+"""Marginal-likelihood gradient steps per second on one MI355X.
+
+Workload (the precision workload the metric is quoted on): n = 434,874 inputs
+x ~ U[-1, 1]^3, targets from a 2,048-feature random-Fourier Matern-3/2 draw
+with length scales U[0.05, 0.2] plus noise sigma = 0.05; s = 64 probe vectors.
+One step = one marginal-likelihood optimisation step of the paper's method:
+pathwise right-hand sides from fixed random features (1,000 sin/cos pairs),
+warm-started CG to relative residual 1e-2 (both mean and probe criteria,
+accepted on the FP32 true residual), the gradient estimate and one Adam step
+(lr 0.03, softplus).  Inputs are resident in HBM before the timed region.
+
+Forms:
+  bf16x3+adjoint  products on bf16 MFMA with hi/lo splitting, FP32 true-residual
+                  acceptance, one fused adjoint pass for the gradient (the value).
+  fp32-plain      FP32 products, d+1 separate derivative-kernel passes for the
+                  gradient (reported alongside with --compare).
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLL-grad steps/s at n=434,874, BF16+adjoint vs FP32 plain, rel-res 1e-2"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+# VALU issue model of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s;
+# an FP32 FMA is one slot (2 flops); v_sqrt_f32 / v_exp_f32 occupy 4 slots each.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", choices=["bf16x3+adjoint", "fp32-plain"], default="bf16x3+adjoint")
+    ap.add_argument("--compare", action="store_true", help="also time the fp32-plain form")
+    ap.add_argument("--n", type=int, default=None, help="override n (smaller runs; not the metric)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1024)
+    return ap.parse_args()
+
+
+def make_inputs(n=None):
+    import torch
+    import workloads as wl
+    from paper_2405_18457_amd import api
+    w = wl.WORKLOADS["D"]
+    n = w.n if n is None else n
+    X = wl.draw_inputs(w, n=n)
+    tr = wl.truth_draws(w, n=n)
+    md = wl.model_pathwise_draws(w, n=n)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    inp = {"w": w, "n": n, "X": dev(X), "t": dev(md["t"]), "W": dev(md["W"]),
+           "w_eps": dev(md["w_eps"]), "Xh": X, "ell": tr["ell"]}
+    theta_true = np.concatenate([tr["ell"], [1.0, w.sigma]])
+    inp["theta_true"] = theta_true
+    return inp, tr, dev
+
+
+def build_targets(ctx, inp, tr, dev):
+    """y = f(x) + sigma * noise, f the data-generating random-feature draw (GPU)."""
+    from paper_2405_18457_amd import api
+    w = inp["w"]
+    F = api.gp_prior_sample(ctx, inp["X"], inp["theta_true"], dev(tr["t"]), dev(tr["w"][:, None]))
+    y = (F[:, 0] + w.sigma * dev(tr["noise"])).contiguous()
+    return y
+
+
+def run_form(ctx, inp, y, form, steps, warmup):
+    import torch
+    from paper_2405_18457_amd import api
+    prec = api.GP_BF16X3 if form == "bf16x3+adjoint" else api.GP_FP32
+    mode = api.GP_ADJ_FUSED if form == "bf16x3+adjoint" else api.GP_ADJ_PER_PARAM
+    cfg = api.solver_cfg(solver=api.GP_CG, tol=1e-2, precision=prec)
+    tr = api.Trainer(ctx, inp["X"], y, inp["theta_true"], api.GP_PATHWISE, cfg, lr=0.03,
+                     s=inp["w"].s, transform=api.GP_SOFTPLUS, warm=True, rff_t=inp["t"],
+                     rff_W=inp["W"], w_eps=inp["w_eps"], adjoint_mode=mode)
+    log = []
+    for k in range(warmup):
+        t0 = time.perf_counter()
+        _, _, st = tr.step()
+        torch.cuda.synchronize()
+        log.append({"phase": "warmup", "s": time.perf_counter() - t0, **_brief(st)})
+        print(f"[bench] {form} warmup {k}: {log[-1]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        _, _, st = tr.step()
+        log.append({"phase": "timed", "s": time.perf_counter() - ts, **_brief(st)})
+        print(f"[bench] {form} step {k}: {log[-1]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = {k: ctx.profile_read(k) for k in range(5)}
+    ctx.profile_enable(False)
+    return elapsed, log, prof, tr
+
+
+def _brief(st):
+    return {"iters": st["iterations"], "matvecs": st["matvecs"], "refine": st["refinements"],
+            "relres_y": round(st["true_relres_y"], 5) if st["true_relres_y"] == st["true_relres_y"]
+            else round(st["relres_y"], 5),
+            "relres_z": round(st["true_relres_z"], 5) if st["true_relres_z"] == st["true_relres_z"]
+            else round(st["relres_z"], 5),
+            "converged": st["converged"]}
+
+
+def roofline(n, d, c, prof):
+    """Dominant kernel: the bf16x3 forward product (class 0)."""
+    ms, cnt = prof[0]
+    if cnt == 0:
+        return None
+    avg_s = ms / cnt / 1e3
+    entries = float(n) * n
+    # Algorithmic VALU work per kernel entry (direct-difference Matern-3/2):
+    # d subtractions + d FMAs for r^2, fma + mul for (1 + ln2 rho) 2^-rho, and
+    # one sqrt + one exp2 at 4 slots each.
+    slots_per_entry = 2 * d + 2 + 2 * 4
+    achieved = entries * slots_per_entry / avg_s          # VALU lane-slots per second
+    mfma_tflops = 2.0 * c * entries / avg_s / 1e12        # algorithmic K*V flops (c = s + 1)
+    return {
+        "bound": "alu",
+        "achieved": round(achieved * 2 / 1e12, 3),        # reported as FP32 TFLOP/s (1 slot = 2 flops)
+        "peak": round(VALU_SLOTS_PER_S * 2 / 1e12, 3),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_SLOTS_PER_S, 4),
+        "traffic": None,
+        "kernel": "kfwd_bf16<BF16X3, D=3, CT=5>",
+        "avg_launch_ms": round(avg_s * 1e3, 3),
+        "launches": cnt,
+        "kernel_entries_per_s": round(entries / avg_s, 1),
+        "mfma_kv_tflops": round(mfma_tflops, 2),
+        "mfma_kv_frac_of_bf16_peak": round(mfma_tflops / BF16_PEAK_TFLOPS, 4),
+    }
+
+
+def cpu_baseline(inp, iters_per_step, rows, y_host=None):
+    """The oracle's matrix-free FP64 product on a bounded row sample, scaled to a step."""
+    import oracle.kernel as ok
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    X = inp["Xh"]
+    n = X.shape[0]
+    theta = inp["theta_true"]
+    V = np.random.default_rng(0).standard_normal((n, inp["w"].s + 1))
+    idx = np.arange(rows)
+    t0 = time.perf_counter()
+    ok.k_matvec(X[idx], X, theta, V)
+    dt = time.perf_counter() - t0
+    t_matvec = dt * n / rows
+    # per step: iterations + initial/true-residual products + one adjoint (~ one product)
+    t_step = (iters_per_step + 3) * t_matvec
+    return {"value": round(1.0 / t_step, 8), "unit": "steps/s", "cores": int(blas_threads),
+            "kind": "oracle",
+            "sample": f"FP64 matrix-free H*V on {rows} of {n} rows x 65 columns took {dt:.2f} s; "
+                      f"full product extrapolated to {t_matvec:.1f} s; step = (CG iterations "
+                      f"{iters_per_step:.1f} + 3) products"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "row-sharded design is described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2405_18457_amd import api
+    torch.cuda.init()
+    ctx = api.Context(0)
+    inp, tr, dev = make_inputs(args.n)
+    y = build_targets(ctx, inp, tr, dev)
+    torch.cuda.synchronize()
+    n, d, s = inp["n"], inp["w"].d, inp["w"].s
+
+    elapsed, log, prof, trainer = run_form(ctx, inp, y, args.form, args.steps, args.warmup)
+    value = args.steps / elapsed
+    timed = [r for r in log if r["phase"] == "timed"]
+    iters = float(np.mean([r["iters"] for r in timed])) if timed else 0.0
+    rec = {
+        "metric": METRIC, "value": round(value, 6), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if args.form == "bf16x3+adjoint" else "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"precision workload: n={n}, d={d}, x~U[-1,1]^3, ell~U[0.05,0.2], "
+                               f"sigma=0.05, s={s}, pathwise + warm start, CG to rel-res 1e-2, "
+                               "Adam lr 0.03, theta0 = data-generating theta",
+                   "form": args.form, "n": n, "d": d, "s": s, "solver": "cg", "tol": 1e-2},
+        "per_step": timed,
+        "warmup_log": [r for r in log if r["phase"] == "warmup"],
+    }
+    if args.form == "bf16x3+adjoint":
+        rec["roofline"] = roofline(n, d, s + 1, prof)
+    rec["kernel_ms"] = {"fwd_bf16": prof[0], "adjoint": prof[1], "rff": prof[2], "cg_vec": prof[3],
+                        "fwd_fp32": prof[4]}
+    if args.compare:
+        e2, log2, prof2, _ = run_form(ctx, inp, y, "fp32-plain", args.steps, args.warmup)
+        rec["fp32_plain"] = {"value": round(args.steps / e2, 6), "unit": "steps/s",
+                             "per_step": [r for r in log2 if r["phase"] == "timed"],
+                             "kernel_ms": {"fwd_fp32": prof2[4]}}
+        rec["bf16x3_over_fp32_plain"] = round(value / (args.steps / e2), 3)
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(inp, iters, args.cpu_rows)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,13 +85,14 @@ const char* gp_last_error(const gp_ctx* ctx);
 /* Library version string, e.g. "gpmi 0.1 gfx950". */
 const char* gp_version(void);
 
-/* Per-launch HIP-event timing of the kernel-matrix product kernels
- * (forward K*V kernels of every precision, including those launched inside
- * gp_solve / gp_mll_grad).  enable != 0 starts recording (and clears totals).
+/* Per-launch HIP-event timing, recorded on the context's stream around the
+ * library's own kernel launches (also those inside gp_solve / gp_mll_grad).
+ * enable != 0 starts recording (and clears totals); enable = 0 stops.
  * gp_profile_read synchronises the stream and returns the summed duration in
- * milliseconds and the launch count of kernel class `which`
- * (0 = forward product, 1 = fused adjoint, 2 = random-feature sample,
- *  3 = solver vector updates).                                               */
+ * milliseconds and the launch count of kernel class `which`:
+ *   0 = forward product in GP_BF16X3 / GP_BF16, 1 = fused adjoint,
+ *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product in GP_FP32.
+ * Errors: GP_ERR_INVALID_ARG for an unknown class.                          */
 int gp_profile_enable(gp_ctx* ctx, int enable);
 int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);
 

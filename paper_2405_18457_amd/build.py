@@ -58,14 +58,30 @@ def _compile(hipcc, src, obj, extra):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
-    """Compile every translation unit (always) and link ``libgpmi.so``."""
+def _stale(src, obj):
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src, os.path.join(CSRC, "gpk.h"), os.path.join(INCLUDE, "gp.h")]
+    return any(os.path.getmtime(p) > t for p in deps)
+
+
+def build(jobs: int | None = None, verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every translation unit and link ``libgpmi.so``.
+
+    By default everything is recompiled; ``incremental=True`` (developer use)
+    recompiles only units whose source or shared headers changed."""
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     units = _jobs()
+    if incremental:
+        todo = [u for u in units if _stale(u[0], u[1])]
+        done = [u[1] for u in units if u not in todo]
+    else:
+        todo, done = units, []
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda u: _compile(hipcc, *u), units))
+        objs = done + list(ex.map(lambda u: _compile(hipcc, *u), todo))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -78,4 +94,4 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)

@@ -33,6 +33,8 @@ namespace {
 
 typedef float f32x8 __attribute__((ext_vector_type(8)));
 
+constexpr int kChunk = 64;  // column steps (x 32 columns) per partial accumulator
+
 template <int D>
 __device__ __forceinline__ float sqdist(const float (&xi)[D], const float (&xj)[D]) {
   float r2 = 0.f;
@@ -127,13 +129,21 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
 #pragma unroll
   for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
-  f32x4 acc[2][CT];
+  f32x4 tot[2][CT], acc[2][CT];
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // Two-level summation: a fresh accumulator per chunk of kChunk column steps,
+  // folded into the running total, keeps FP32 chains short at large n.
+  for (int64_t c0 = s0; c0 < s1; c0 += kChunk) {
+  const int64_t c1 = c0 + kChunk < s1 ? c0 + kChunk : s1;
 #pragma unroll
   for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t st = s0; st < s1; ++st) {
+  for (int64_t st = c0; st < c1; ++st) {
     float xj[8][D];
     const float* xb = xp2 + (st * kJStep + 8 * g) * DP;
 #pragma unroll
@@ -163,7 +173,12 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
       }
     }
   }
-  epilogue<CT>(acc, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] += acc[rs][ct];
+  }
+  epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
 }
 
 template <int D, int CT, int FN>
@@ -187,13 +202,19 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
 #pragma unroll
   for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
-  f32x4 acc[2][CT];
+  f32x4 tot[2][CT], acc[2][CT];
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t c0 = s0; c0 < s1; c0 += kChunk) {
+  const int64_t c1 = c0 + kChunk < s1 ? c0 + kChunk : s1;
 #pragma unroll
   for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int64_t st = s0; st < s1; ++st) {
+  for (int64_t st = c0; st < c1; ++st) {
     float xj[8][D];
     const float* xb = xp2 + (st * kJStep + g) * DP;
 #pragma unroll
@@ -218,7 +239,12 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
           acc[rs][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, b[ct][kk], acc[rs][ct], 0, 0, 0);
       }
   }
-  epilogue<CT>(acc, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] += acc[rs][ct];
+  }
+  epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
 }
 
 template <int D, int CT>

