@@ -78,9 +78,10 @@ def _dptr(t: torch.Tensor | None, name: str, cols: int | None = None):
         if t.stride(0) != 1:
             raise ValueError(f"{name} must be contiguous")
         return C.c_void_p(t.data_ptr()), 1
-    if t.dim() != 2 or t.stride(1) != 1:
+    if t.dim() != 2 or (t.stride(1) != 1 and t.shape[1] > 1):
         raise ValueError(f"{name} must be a row-major 2-D tensor with unit column stride")
-    return C.c_void_p(t.data_ptr()), t.stride(0)
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return C.c_void_p(t.data_ptr()), max(ld, t.shape[1])
 
 
 def _theta(theta):

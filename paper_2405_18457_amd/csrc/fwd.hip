@@ -23,6 +23,18 @@
 //     A operand (row = lane % 16, k = lane / 16) and V in a 32x16 tile order
 //     that gives each lane 8 consecutive floats per step.
 //
+// Software pipeline.  The VALU (distances, sqrt, exp2) and the matrix cores
+// are separate units; one wave keeps both busy by interleaving, in every
+// half-step, the MFMAs of one row sub-tile with the VALU work that produces
+// the next sub-tile's A operand:
+//     half-step k:  VALU A(rs1, step k)      ||  MFMA  acc[rs0] += A(rs0, k) B(k)
+//                   VALU A(rs0, step k+1)    ||  MFMA  acc[rs1] += A(rs1, k) B(k)
+// The step loop is unrolled by two with swapped register buffers (no register
+// copies); the next step's coordinates are loaded at the start of a step and
+// each V tile is reloaded for the next step right after its last MFMA use.
+//
+// Accuracy: a fresh accumulator per chunk of kChunk column steps is folded
+// into a running total (two-level summation keeps FP32 chains short at large n).
 // For small n the column range is split over S workgroups per row block and a
 // second kernel sums the S partial tiles in a fixed order (deterministic).
 #include "gpk.h"
@@ -31,9 +43,15 @@ namespace gpk {
 
 namespace {
 
-typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kChunk = 64;  // column steps (x 32 columns) per partial accumulator
+
+// sched_group_barrier masks
+constexpr int kMaskVALU = 0x002;
+constexpr int kMaskMFMA = 0x008;
+constexpr int kMaskVMEMRead = 0x020;
 
 template <int D>
 __device__ __forceinline__ float sqdist(const float (&xi)[D], const float (&xj)[D]) {
@@ -80,6 +98,84 @@ __device__ __forceinline__ void load_point(const float* __restrict__ p, float (&
   }
 }
 
+// A operand of one 16 x 32 kernel tile: the lane's row against its 8 columns,
+// rounded to bf16 (hi, RNE) and, for BF16X3, the bf16 rounding of the remainder.
+template <int MODE, int D>
+__device__ __forceinline__ void tile_a(const float (&xi)[D], const float (&xj)[8][D], bf16x8& ah,
+                                       bf16x8& al) {
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const float m0 = matern_r2(sqdist<D>(xi, xj[e]));
+    const float m1 = matern_r2(sqdist<D>(xi, xj[e + 1]));
+    const bf16x2 h = __builtin_convertvector((f32x2){m0, m1}, bf16x2);
+    ah[e] = h[0];
+    ah[e + 1] = h[1];
+    if (MODE == P_BF16X3) {
+      const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+      const float h0 = __builtin_bit_cast(float, hb << 16);
+      const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+      const bf16x2 l = __builtin_convertvector((f32x2){m0 - h0, m1 - h1}, bf16x2);
+      al[e] = l[0];
+      al[e + 1] = l[1];
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void mfma3(f32x4& acc, const bf16x8& ah, const bf16x8& al,
+                                      const bf16x8& bh, const bf16x8& bl) {
+  if (MODE == P_BF16X3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  }
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+// Interleave NMFMA MFMAs with the VALU work of the same scheduling region.
+template <int NMFMA, int NVALU>
+__device__ __forceinline__ void interleave() {
+#pragma unroll
+  for (int i = 0; i < NMFMA; ++i) {
+    __builtin_amdgcn_sched_group_barrier(kMaskMFMA, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(kMaskVALU, NVALU, 0);
+  }
+}
+
+// One column step of the bf16 pipeline (see file comment).  xc/bh/bl/a0 hold
+// step k; xn receives step k+1's coordinates, n0 its rs0 A operand, and bh/bl
+// are refilled with step k+1's V tiles.
+template <int MODE, int D, int CT>
+__device__ __forceinline__ void bf16_step(const float (&xi)[2][D], const float (&xc)[8][D],
+                                          float (&xn)[8][D], bf16x8 (&bh)[CT], bf16x8 (&bl)[CT],
+                                          const bf16x8& a0h, const bf16x8& a0l, bf16x8& n0h,
+                                          bf16x8& n0l, f32x4 (&acc)[2][CT],
+                                          const float* __restrict__ xnext,
+                                          const uint16_t* __restrict__ vh_next,
+                                          const uint16_t* __restrict__ vl_next) {
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) load_point<D>(xnext + e * DP, xn[e]);
+  // half 1: A(rs1, k) on the VALU while acc[rs0] accumulates on the matrix cores
+  bf16x8 a1h, a1l;
+  tile_a<MODE, D>(xi[1], xc, a1h, a1l);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) mfma3<MODE>(acc[0][ct], a0h, a0l, bh[ct], bl[ct]);
+  __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
+  interleave<NM, (MODE == P_BF16X3 ? 6 : 12)>();
+  __builtin_amdgcn_sched_barrier(0);
+  // half 2: A(rs0, k+1) on the VALU while acc[rs1] accumulates; V tiles refilled
+  tile_a<MODE, D>(xi[0], xn, n0h, n0l);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    mfma3<MODE>(acc[1][ct], a1h, a1l, bh[ct], bl[ct]);
+    bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
+    if (MODE == P_BF16X3) bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
+  }
+  interleave<NM, (MODE == P_BF16X3 ? 6 : 12)>();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int CT>
 __device__ __forceinline__ void epilogue(const f32x4 (&acc)[2][CT], int64_t row0, int l16, int g,
                                          int64_t n1, int64_t n1_pad, int c, int S, int64_t sp,
@@ -107,6 +203,25 @@ __device__ __forceinline__ void epilogue(const f32x4 (&acc)[2][CT], int64_t row0
       }
 }
 
+template <int CT>
+__device__ __forceinline__ void zero(f32x4 (&a)[2][CT]) {
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) a[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+template <int CT>
+__device__ __forceinline__ void fold(f32x4 (&tot)[2][CT], f32x4 (&acc)[2][CT]) {
+#pragma unroll
+  for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      tot[rs][ct] += acc[rs][ct];
+      acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 template <int MODE, int D, int CT>
 __global__ __launch_bounds__(256, 2) void kfwd_bf16(
     const float* __restrict__ xp1, const float* __restrict__ xp2,
@@ -130,55 +245,96 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
   for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
   f32x4 tot[2][CT], acc[2][CT];
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  zero<CT>(tot);
+  zero<CT>(acc);
 
-  // Two-level summation: a fresh accumulator per chunk of kChunk column steps,
-  // folded into the running total, keeps FP32 chains short at large n.
-  for (int64_t c0 = s0; c0 < s1; c0 += kChunk) {
-  const int64_t c1 = c0 + kChunk < s1 ? c0 + kChunk : s1;
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t st = c0; st < c1; ++st) {
-    float xj[8][D];
-    const float* xb = xp2 + (st * kJStep + 8 * g) * DP;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) load_point<D>(xb + e * DP, xj[e]);
-    const int64_t toff = st * CT * 512 + l16 * 32 + 8 * g;
+  if (s0 < s1) {
+    // per-lane offsets: coordinates of columns 8g..8g+7, V tile element (col l16, rows 8g..)
+    const float* xb = xp2 + 8 * g * DP;
+    const int64_t voff = l16 * 32 + 8 * g;
+    const int64_t tstride = (int64_t)CT * 512;
+    float X0[8][D], X1[8][D];
     bf16x8 bh[CT], bl[CT];
+    bf16x8 A0h, A0l, A1h, A1l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) load_point<D>(xb + (s0 * kJStep + e) * DP, X0[e]);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      bh[ct] = *reinterpret_cast<const bf16x8*>(vhi + toff + ct * 512);
-      if (MODE == P_BF16X3) bl[ct] = *reinterpret_cast<const bf16x8*>(vlo + toff + ct * 512);
+      bh[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
+      if (MODE == P_BF16X3)
+        bl[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
     }
-#pragma unroll
-    for (int rs = 0; rs < 2; ++rs) {
-      f32x8 m;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) m[e] = matern_r2(sqdist<D>(xi[rs], xj[e]));
-      const bf16x8 ah = __builtin_convertvector(m, bf16x8);
-      bf16x8 al;
-      if (MODE == P_BF16X3) al = __builtin_convertvector(m - __builtin_convertvector(ah, f32x8), bf16x8);
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        if (MODE == P_BF16X3) {
-          acc[rs][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[rs][ct], 0, 0, 0);
-          acc[rs][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[rs][ct], 0, 0, 0);
-        }
-        acc[rs][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[rs][ct], 0, 0, 0);
+    tile_a<MODE, D>(xi[0], X0, A0h, A0l);
+    int64_t st = s0;
+    int left = kChunk;
+    while (true) {
+      int64_t nx = st + 1 < s1 ? st + 1 : st;
+      bf16_step<MODE, D, CT>(xi, X0, X1, bh, bl, A0h, A0l, A1h, A1l, acc,
+                             xb + nx * kJStep * DP, vhi + nx * tstride + voff,
+                             vlo + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT>(tot, acc);
+        left = kChunk;
+      }
+      nx = st + 1 < s1 ? st + 1 : st;
+      bf16_step<MODE, D, CT>(xi, X1, X0, bh, bl, A1h, A1l, A0h, A0l, acc,
+                             xb + nx * kJStep * DP, vhi + nx * tstride + voff,
+                             vlo + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT>(tot, acc);
+        left = kChunk;
       }
     }
-  }
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] += acc[rs][ct];
+    fold<CT>(tot, acc);
   }
   epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
+}
+
+// FP32 pipeline: same structure with 8 scalar A operands per row sub-tile and
+// 8 K=4 MFMAs per 16-column tile per step.
+template <int D, int FN>
+__device__ __forceinline__ void f32_vals(const float (&xi)[D], const float (&xj)[8][D], int fd,
+                                         float (&m)[8]) {
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+    m[kk] = (FN == FN_MATERN) ? matern_r2(sqdist<D>(xi, xj[kk])) : dlen_val<D>(xi, xj[kk], fd);
+}
+
+template <int D, int CT, int FN>
+__device__ __forceinline__ void f32_step(const float (&xi)[2][D], const float (&xc)[8][D],
+                                         float (&xn)[8][D], float (&b)[CT][8],
+                                         const float (&a0)[8], float (&n0)[8],
+                                         f32x4 (&acc)[2][CT], int fd,
+                                         const float* __restrict__ xnext,
+                                         const float* __restrict__ vnext) {
+  constexpr int DP = (D + 3) & ~3;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) load_point<D>(xnext + 4 * kk * DP, xn[kk]);
+  float a1[8];
+  f32_vals<D, FN>(xi[1], xc, fd, a1);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+      acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[kk], b[ct][kk], acc[0][ct], 0, 0, 0);
+  __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
+  interleave<8 * CT, 2>();
+  __builtin_amdgcn_sched_barrier(0);
+  f32_vals<D, FN>(xi[0], xn, fd, n0);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+      acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[kk], b[ct][kk], acc[1][ct], 0, 0, 0);
+    const float4 lo4 = *reinterpret_cast<const float4*>(vnext + ct * 512);
+    const float4 hi4 = *reinterpret_cast<const float4*>(vnext + ct * 512 + 4);
+    b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
+    b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
+  }
+  interleave<8 * CT, 2>();
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int D, int CT, int FN>
@@ -203,46 +359,49 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
   for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
   f32x4 tot[2][CT], acc[2][CT];
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  zero<CT>(tot);
+  zero<CT>(acc);
 
-  for (int64_t c0 = s0; c0 < s1; c0 += kChunk) {
-  const int64_t c1 = c0 + kChunk < s1 ? c0 + kChunk : s1;
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t st = c0; st < c1; ++st) {
-    float xj[8][D];
-    const float* xb = xp2 + (st * kJStep + g) * DP;
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) load_point<D>(xb + 4 * kk * DP, xj[kk]);
+  if (s0 < s1) {
+    // per-lane offsets: columns g + 4 kk, V tile element (col l16, rows g + 4 kk)
+    const float* xb = xp2 + g * DP;
+    const int64_t voff = (l16 * 4 + g) * 8;
+    const int64_t tstride = (int64_t)CT * 512;
+    float X0[8][D], X1[8][D];
     float b[CT][8];
-    const float* tb = vf + st * CT * 512 + (l16 * 4 + g) * 8;
+    float A0[8], A1[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) load_point<D>(xb + (s0 * kJStep + 4 * kk) * DP, X0[kk]);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const float4 lo4 = *reinterpret_cast<const float4*>(tb + ct * 512);
-      const float4 hi4 = *reinterpret_cast<const float4*>(tb + ct * 512 + 4);
+      const float* p = vf + s0 * tstride + voff + ct * 512;
+      const float4 lo4 = *reinterpret_cast<const float4*>(p);
+      const float4 hi4 = *reinterpret_cast<const float4*>(p + 4);
       b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
       b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
     }
-#pragma unroll
-    for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const float m = (FN == FN_MATERN) ? matern_r2(sqdist<D>(xi[rs], xj[kk]))
-                                          : dlen_val<D>(xi[rs], xj[kk], fn_dim);
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-          acc[rs][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, b[ct][kk], acc[rs][ct], 0, 0, 0);
+    f32_vals<D, FN>(xi[0], X0, fn_dim, A0);
+    int64_t st = s0;
+    int left = kChunk;
+    while (true) {
+      int64_t nx = st + 1 < s1 ? st + 1 : st;
+      f32_step<D, CT, FN>(xi, X0, X1, b, A0, A1, acc, fn_dim, xb + nx * kJStep * DP,
+                          vf + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT>(tot, acc);
+        left = kChunk;
       }
-  }
-#pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) tot[rs][ct] += acc[rs][ct];
+      nx = st + 1 < s1 ? st + 1 : st;
+      f32_step<D, CT, FN>(xi, X1, X0, b, A1, A0, acc, fn_dim, xb + nx * kJStep * DP,
+                          vf + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT>(tot, acc);
+        left = kChunk;
+      }
+    }
+    fold<CT>(tot, acc);
   }
   epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
 }
@@ -256,7 +415,7 @@ hipError_t launch(const FwdArgs& a, hipStream_t st) {
                        a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
   } else if (a.prec == P_BF16) {
     hipLaunchKernelGGL((kfwd_bf16<P_BF16, D, CT>), grid, dim3(256), 0, st, a.xp1, a.xp2,
-                       (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad, a.steps,
+                       (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1, a.n1_pad, a.steps,
                        a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
   } else if (a.fn == FN_MATERN) {
     hipLaunchKernelGGL((kfwd_f32<D, CT, FN_MATERN>), grid, dim3(256), 0, st, a.xp1, a.xp2,

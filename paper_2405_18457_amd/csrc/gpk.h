@@ -195,4 +195,24 @@ hipError_t fill(float* dst, int64_t count, float v, hipStream_t st);
 hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* status,
                         hipStream_t st);
 
+// ---------------------------------------------------------------- AP / SGD (solve.hip)
+constexpr int kMaxAPBlock = 2016;  // padded AP block size limit (multiple of 32)
+// FP64 H[I, I] for every contiguous block of b rows, lower triangle, padded to P x P.
+hipError_t ap_build_blocks(const float* xp, int DP, int d, int64_t n, int b, int P, double a2,
+                           double s2, double* M, hipStream_t st);
+// In-place lower Cholesky of nblk P x P blocks; status bit 2 on a non-positive pivot.
+hipError_t ap_cholesky(double* M, int nblk, int P, int* status, hipStream_t st);
+// out[i, :c] = H[I_blk, I_blk]^-1 R[I_blk, :c] from the cached factor.
+hipError_t ap_solve_block(const double* M, int P, int blk, int b, int64_t n, const float* R,
+                          int64_t ldr, int c, float* out, int64_t ldo, hipStream_t st);
+// scores[k] = || sum_c R[I_k, c] ||^2
+hipError_t ap_scores(const float* R, int64_t ld, int64_t n, int b, int c, double* scores,
+                     hipStream_t st);
+// Y[base + i, :] += alpha X[i, :] for i < bk
+hipError_t add_block(float* Y, int64_t ldy, int64_t base, int bk, const float* X, int64_t ldx,
+                     int c, float alpha, hipStream_t st);
+// G[i, :] += s2 Ut[idx[i], :] - Bt[idx[i], :]
+hipError_t sgd_fix(float* G, int64_t ldg, const float* Ut, const float* Bt, int64_t ld,
+                   const int32_t* idx, int64_t b, int c, float s2, hipStream_t st);
+
 }  // namespace gpk

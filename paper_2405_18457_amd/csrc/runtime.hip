@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -317,6 +319,26 @@ int status_to_error(gp_ctx* ctx, int st) {
 
 bool keep_going(double ry, double rz, double tol) { return ry > tol || rz > tol; }
 
+// Opt-in progress lines on stderr for long solves: GPMI_PROGRESS=<seconds>.
+struct Progress {
+  double every = 0.0;
+  std::chrono::steady_clock::time_point start, last;
+  Progress() {
+    const char* e = std::getenv("GPMI_PROGRESS");
+    if (e) every = std::atof(e);
+    start = last = std::chrono::steady_clock::now();
+  }
+  void tick(const char* what, int64_t it, double ry, double rz) {
+    if (every <= 0.0) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - last).count() < every) return;
+    last = now;
+    std::fprintf(stderr, "[gpmi] %s iter %lld  relres_y %.3e  relres_z %.3e  (%.1f s)\n", what,
+                 (long long)it, ry, rz, std::chrono::duration<double>(now - start).count());
+    std::fflush(stderr);
+  }
+};
+
 // Allocate solver vectors and normalise: Bt = B / (||B|| + eps), Ut = U0 / (||B|| + eps).
 int solve_setup(gp_ctx* ctx, const float* B, int64_t ldb, const float* U, int64_t ldu,
                 int64_t n, int c, SolveState& s) {
@@ -379,10 +401,12 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
   double ry = 0, rz = 0;
   double last_true = std::numeric_limits<double>::infinity();
   int st = 0;
+  Progress prog;
   while (true) {
     if (since_true == 0 || t % check == 0 || t >= cap) {
       CHK(read_norms(ctx, s, &ry, &rz, &st));
       CHK(status_to_error(ctx, st));
+      prog.tick("cg", t, ry, rz);
       bool go = keep_going(ry, rz, cfg.tol);
       if (since_true == 0 && t == 0) last_true = std::max(ry, rz);
       if (!go && mixed && since_true > 0) {
@@ -446,6 +470,176 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
   stats.epochs = (double)t;
   stats.relres_y = ry;
   stats.relres_z = rz;
+  return GP_OK;
+}
+
+// Column norms of R into s.rnorm (and the stop-test values on the host).
+int residual_norms(gp_ctx* ctx, SolveState& s, double* ry, double* rz, int* st) {
+  HIPCHK(col_dot_partial(s.R, nullptr, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+  HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, nullptr, s.rnorm, s.status, ctx->stream));
+  return read_norms(ctx, s, ry, rz, st);
+}
+
+// FP32 true residual of the current iterate (for the statistics), leaving R intact.
+int true_residual_stats(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
+                        gp_solve_stats& stats) {
+  float* T;
+  CHK(ensure(ctx, B_AUX, (size_t)s.n * s.c, &T));
+  CHK(kprod(ctx, px, px, s.Ut, s.c, s.c, s.HD, s.c, GP_FP32, a2_of(theta, d), s.Ut, s.c,
+            s2_of(theta, d)));
+  HIPCHK(residual_init(s.Bt, s.HD, T, nullptr, s.n, s.c, s.c, s.partial, s.nb, false,
+                       ctx->stream));
+  HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, nullptr, s.rnorm, s.status, ctx->stream));
+  int st = 0;
+  CHK(read_norms(ctx, s, &stats.true_relres_y, &stats.true_relres_z, &st));
+  stats.matvecs += 1;
+  return status_to_error(ctx, st);
+}
+
+// Alternating projections (App. B, Algorithm 2).
+int ap_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
+             SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
+  const int64_t n = s.n;
+  const int c = s.c;
+  const int b = (int)std::min<int64_t>(cfg.ap_block, n);
+  if (b < 1) return fail(ctx, GP_ERR_INVALID_ARG, "ap_block must be >= 1");
+  const int P = (int)round_up(b, 32);
+  if (P > kMaxAPBlock)
+    return fail(ctx, GP_ERR_INVALID_ARG, "ap_block %d exceeds the supported %d", b, kMaxAPBlock);
+  const int nblk = (int)((n + b - 1) / b);
+  const double limit = cfg.max_epochs > 0 ? (double)n / b * cfg.max_epochs
+                                          : (double)kSafetyCap * nblk;
+  const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
+  // Factor every diagonal block once (cached for this solve).
+  double* M;
+  CHK(ensure(ctx, B_APF, (size_t)nblk * P * P, &M));
+  HIPCHK(ap_build_blocks(px.xp, px.DP, d, n, b, P, (double)theta[d] * theta[d],
+                         (double)theta[d + 1] * theta[d + 1], M, ctx->stream));
+  HIPCHK(ap_cholesky(M, nblk, P, s.status, ctx->stream));
+  // r = b~ - H u~ (FP32)
+  CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
+  stats.matvecs += 1;
+  float *delta, *G;
+  CHK(ensure(ctx, B_G, (size_t)P * c, &delta));
+  CHK(ensure(ctx, B_AUX, (size_t)n * c, &G));
+  double* scores;
+  CHK(ensure(ctx, B_ADJP, (size_t)nblk, &scores));
+  CHK(ensure_pinned(ctx, (size_t)kMaxC + 2 + nblk));
+  Packed pb;  // the selected block's points as kernel columns
+  int64_t t = 0;
+  double ry = 0, rz = 0;
+  int st = 0;
+  Progress prog;
+  while (true) {
+    HIPCHK(ap_scores(s.R, c, n, b, c, scores, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->hpin + kMaxC + 2, scores, nblk * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    CHK(residual_norms(ctx, s, &ry, &rz, &st));
+    CHK(status_to_error(ctx, st));
+    prog.tick("ap", t, ry, rz);
+    if (!keep_going(ry, rz, cfg.tol) || !((double)t < limit)) {
+      stats.converged = !keep_going(ry, rz, cfg.tol);
+      break;
+    }
+    int k = 0;
+    const double* sc = ctx->hpin + kMaxC + 2;
+    for (int q = 1; q < nblk; ++q)
+      if (sc[q] > sc[k]) k = q;
+    const int64_t base = (int64_t)k * b;
+    const int bk = (int)std::min<int64_t>(b, n - base);
+    // delta = H[I,I]^-1 r[I];  u[I] += delta;  r -= H[:, I] delta
+    HIPCHK(ap_solve_block(M, P, k, b, n, s.R, c, c, delta, c, ctx->stream));
+    HIPCHK(add_block(s.Ut, c, base, bk, delta, c, c, 1.f, ctx->stream));
+    CHK(pack_points(ctx, B_XP2, X + base * d, nullptr, bk, d, theta, &pb));
+    CHK(kprod(ctx, px, pb, delta, c, c, G, c, cfg.precision, a2, nullptr, 0, 0.f));
+    HIPCHK(axpy_cols(s.R, G, n, c, c, -1.f, ctx->stream));
+    HIPCHK(add_block(s.R, c, base, bk, delta, c, c, -s2, ctx->stream));
+    ++t;
+  }
+  stats.iterations = t;
+  stats.epochs = (double)t * b / n;
+  stats.relres_y = ry;
+  stats.relres_z = rz;
+  if (t > 0) CHK(true_residual_stats(ctx, px, theta, d, s, stats));
+  return GP_OK;
+}
+
+// Floyd's sampling of b distinct indices from [0, n).
+void draw_batch(std::mt19937_64& rng, int64_t n, int b, int32_t* out, std::vector<char>& seen) {
+  if ((int64_t)seen.size() != n) seen.assign(n, 0);
+  int cnt = 0;
+  for (int64_t j = n - b; j < n; ++j) {
+    std::uniform_int_distribution<int64_t> dist(0, j);
+    int64_t v = dist(rng);
+    if (seen[v]) v = j;
+    seen[v] = 1;
+    out[cnt++] = (int32_t)v;
+  }
+  for (int q = 0; q < cnt; ++q) seen[out[q]] = 0;
+}
+
+// Stochastic gradient descent (App. B, Algorithm 3).
+int sgd_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
+              SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
+  const int64_t n = s.n;
+  const int c = s.c;
+  const int b = (int)std::min<int64_t>(cfg.sgd_batch, n);
+  if (b < 1) return fail(ctx, GP_ERR_INVALID_ARG, "sgd_batch must be >= 1");
+  double limit = cfg.max_epochs > 0 ? (double)n / b * cfg.max_epochs : (double)kSafetyCap;
+  if (cfg.sgd_batches) limit = std::min(limit, (double)cfg.sgd_batches_count);
+  const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
+  float *Mom, *G;
+  int32_t* idx;
+  CHK(ensure(ctx, B_MOM, (size_t)n * c, &Mom));
+  CHK(ensure(ctx, B_G, (size_t)round_up(b, kRowAlign) * c, &G));
+  CHK(ensure(ctx, B_IDX, (size_t)b * 2, &idx));
+  HIPCHK(fill(Mom, n * c, 0.f, ctx->stream));
+  // residual estimate starts at b~ (as printed, also under warm start)
+  HIPCHK(copy_cols(s.Bt, c, n, c, s.R, c, ctx->stream));
+  CHK(ensure_pinned(ctx, (size_t)kMaxC + 2 + b));
+  int32_t* hidx = reinterpret_cast<int32_t*>(ctx->hpin + kMaxC + 2);
+  std::mt19937_64 rng(cfg.sgd_seed);
+  std::vector<char> seen;
+  int64_t t = 0;
+  double ry = 0, rz = 0;
+  int st = 0;
+  Progress prog;
+  while (true) {
+    CHK(residual_norms(ctx, s, &ry, &rz, &st));
+    CHK(status_to_error(ctx, st));
+    prog.tick("sgd", t, ry, rz);
+    if (!keep_going(ry, rz, cfg.tol) || !((double)t < limit)) {
+      stats.converged = !keep_going(ry, rz, cfg.tol);
+      break;
+    }
+    if (cfg.sgd_batches) {
+      const int32_t* src = cfg.sgd_batches + t * b;
+      for (int q = 0; q < b; ++q) {
+        if (src[q] < 0 || src[q] >= n)
+          return fail(ctx, GP_ERR_INVALID_ARG, "sgd batch index %d out of range", src[q]);
+        hidx[q] = src[q];
+      }
+    } else {
+      draw_batch(rng, n, b, hidx, seen);
+    }
+    // the pinned staging buffer is reused next iteration after the norm read syncs
+    HIPCHK(hipMemcpyAsync(idx, hidx, b * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    Packed pr;
+    CHK(pack_points(ctx, B_XP2, X, idx, b, d, theta, &pr));
+    // g[I] = H[I, :] u - b~[I]
+    CHK(kprod(ctx, pr, px, s.Ut, c, c, G, c, cfg.precision, a2, nullptr, 0, 0.f));
+    HIPCHK(sgd_fix(G, c, s.Ut, s.Bt, c, idx, b, c, s2, ctx->stream));
+    // m = rho m - (gamma/b) g;  u += m;  r[I] = g[I]
+    HIPCHK(sgd_momentum(Mom, G, idx, b, n, c, c, (float)cfg.sgd_momentum,
+                        (float)(cfg.sgd_lr / b), ctx->stream));
+    HIPCHK(sgd_finish(s.Ut, s.R, Mom, G, idx, b, n, c, c, ctx->stream));
+    ++t;
+  }
+  stats.iterations = t;
+  stats.epochs = (double)t * b / n;
+  stats.relres_y = ry;
+  stats.relres_z = rz;
+  if (t > 0) CHK(true_residual_stats(ctx, px, theta, d, s, stats));
   return GP_OK;
 }
 
@@ -876,12 +1070,17 @@ namespace {
 int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
                    const float* B, int64_t ldb, float* U, int64_t ldu, int c,
                    const gp_solver_cfg& cfg, gp_solve_stats& stats) {
-  (void)X;
   SolveState s;
   CHK(solve_setup(ctx, B, ldb, U, ldu, px.n, c, s));
   switch (cfg.solver) {
     case GP_CG:
       CHK(cg_solve(ctx, px, theta, d, s, cfg, stats));
+      break;
+    case GP_AP:
+      CHK(ap_solve(ctx, px, X, theta, d, s, cfg, stats));
+      break;
+    case GP_SGD:
+      CHK(sgd_solve(ctx, px, X, theta, d, s, cfg, stats));
       break;
     default:
       return fail(ctx, GP_ERR_INVALID_ARG, "solver %d not available", cfg.solver);
