@@ -50,7 +50,38 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs; not the metric)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
+                    help="only time K launches of the forward product on the bench inputs "
+                         "(65 columns, same launch configuration); for profilers")
+    ap.add_argument("--precision", choices=["bf16x3", "fp32", "bf16"], default="bf16x3",
+                    help="product precision for --kernel-only")
     return ap.parse_args()
+
+
+def kernel_only(args):
+    import torch
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    inp, _, dev = make_inputs(args.n)
+    n = inp["n"]
+    prec = {"bf16x3": api.GP_BF16X3, "fp32": api.GP_FP32, "bf16": api.GP_BF16}[args.precision]
+    V = dev(np.random.default_rng(1).standard_normal((n, inp["w"].s + 1)).astype(np.float32))
+    out = torch.empty_like(V)
+    api.gp_kmatvec(ctx, inp["X"], inp["X"], inp["theta_true"], V, prec, True, out)  # warm
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.kernel_only):
+        api.gp_kmatvec(ctx, inp["X"], inp["X"], inp["theta_true"], V, prec, True, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, cnt = ctx.profile_read(4 if prec == api.GP_FP32 else 0)
+    ctx.profile_enable(False)
+    print(json.dumps({"kernel_only": args.precision, "n": n, "launches": cnt,
+                      "avg_kernel_ms": round(ms / max(cnt, 1), 3),
+                      "avg_call_ms": round(1e3 * wall / max(args.kernel_only, 1), 3),
+                      "kernel_entries_per_s": float(n) * n / (ms / max(cnt, 1) / 1e3)}),
+          flush=True)
 
 
 def make_inputs(n=None):
@@ -167,7 +198,7 @@ def cpu_baseline(inp, iters_per_step, rows, y_host=None):
     t_matvec = dt * n / rows
     # per step: iterations + initial/true-residual products + one adjoint (~ one product)
     t_step = (iters_per_step + 3) * t_matvec
-    return {"value": round(1.0 / t_step, 8), "unit": "steps/s", "cores": int(blas_threads),
+    return {"value": float(f"{1.0 / t_step:.4g}"), "unit": "steps/s", "cores": int(blas_threads),
             "kind": "oracle",
             "sample": f"FP64 matrix-free H*V on {rows} of {n} rows x 65 columns took {dt:.2f} s; "
                       f"full product extrapolated to {t_matvec:.1f} s; step = (CG iterations "
@@ -180,6 +211,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "row-sharded design is described in DESIGN.md and not run here.", file=sys.stderr)
         sys.exit(2)
+    if args.kernel_only:
+        kernel_only(args)
+        return
     import torch
     from paper_2405_18457_amd import api
     torch.cuda.init()

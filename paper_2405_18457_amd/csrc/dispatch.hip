@@ -71,7 +71,6 @@ int choose_splits(int64_t rowblocks, int64_t steps) {
 }
 
 hipError_t fwd(const FwdArgs& a, hipStream_t st) {
-  if (a.n1_pad % kFwdRowsPerWG) return hipErrorInvalidValue;
   switch (a.D) {
     case 1: return fwd_d1(a, st);
     case 2: return fwd_d2(a, st);

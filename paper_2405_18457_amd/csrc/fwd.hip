@@ -4,8 +4,11 @@
 // never stored (the paper's regularised kernel matrix, Sec. 2; App. B counts
 // one "epoch" as computing every entry once).  Work split:
 //
-//   * one workgroup = 4 waves = 128 output rows; every wave owns 2 row
-//     sub-tiles of 16 rows and streams the kernel columns j in steps of 32;
+//   * one workgroup = 4 waves; every wave owns RS row sub-tiles of 16 rows
+//     (RS = 4 for up to 80 columns, 2 above: more rows per wave reuse every
+//     loaded V tile and coordinate more often, which keeps the vector-L1
+//     load traffic well below its throughput) and streams the kernel columns
+//     j in steps of 32;
 //   * per step each lane evaluates 8 kernel values of one row i (lane % 16)
 //     against 8 consecutive columns j (8 * (lane / 16) + e) with direct
 //     coordinate differences in FP32 (no norm expansion, so no cancellation),
@@ -27,8 +30,8 @@
 // are separate units; one wave keeps both busy by interleaving, in every
 // half-step, the MFMAs of one row sub-tile with the VALU work that produces
 // the next sub-tile's A operand:
-//     half-step k:  VALU A(rs1, step k)      ||  MFMA  acc[rs0] += A(rs0, k) B(k)
-//                   VALU A(rs0, step k+1)    ||  MFMA  acc[rs1] += A(rs1, k) B(k)
+//     sub-tile r < RS-1:  VALU A(r+1, step k)   ||  MFMA  acc[r] += A(r, k) B(k)
+//     sub-tile RS-1:      VALU A(0, step k+1)   ||  MFMA  acc[RS-1] += A(RS-1, k) B(k)
 // The step loop is unrolled by two with swapped register buffers (no register
 // copies); the next step's coordinates are loaded at the start of a step and
 // each V tile is reloaded for the next step right after its last MFMA use.
@@ -121,14 +124,23 @@ __device__ __forceinline__ void tile_a(const float (&xi)[D], const float (&xj)[8
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ void mfma3(f32x4& acc, const bf16x8& ah, const bf16x8& al,
-                                      const bf16x8& bh, const bf16x8& bl) {
+// acc[ct] += A B[ct] for all column tiles; for BF16X3 the three partial products
+// (lo*hi, hi*lo, hi*hi; small terms first) are issued as three passes over the
+// tiles so that dependent accumulations into one tile are CT instructions apart.
+template <int MODE, int CT>
+__device__ __forceinline__ void mfma_tiles(f32x4 (&acc)[CT], const bf16x8& ah, const bf16x8& al,
+                                           const bf16x8 (&bh)[CT], const bf16x8 (&bl)[CT]) {
   if (MODE == P_BF16X3) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[ct], 0, 0, 0);
   }
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[ct], 0, 0, 0);
 }
 
 // Interleave NMFMA MFMAs with the VALU work of the same scheduling region.
@@ -142,49 +154,67 @@ __device__ __forceinline__ void interleave() {
 }
 
 // One column step of the bf16 pipeline (see file comment).  xc/bh/bl/a0 hold
-// step k; xn receives step k+1's coordinates, n0 its rs0 A operand, and bh/bl
-// are refilled with step k+1's V tiles.
-template <int MODE, int D, int CT>
-__device__ __forceinline__ void bf16_step(const float (&xi)[2][D], const float (&xc)[8][D],
+// step k; xn receives step k+1's coordinates, n0 the A operand of sub-tile 0
+// for step k+1, and bh/bl are refilled with step k+1's V tiles.
+template <int MODE, int D, int CT, int RS>
+__device__ __forceinline__ void bf16_step(const float (&xi)[RS][D], const float (&xc)[8][D],
                                           float (&xn)[8][D], bf16x8 (&bh)[CT], bf16x8 (&bl)[CT],
                                           const bf16x8& a0h, const bf16x8& a0l, bf16x8& n0h,
-                                          bf16x8& n0l, f32x4 (&acc)[2][CT],
+                                          bf16x8& n0l, f32x4 (&acc)[RS][CT],
                                           const float* __restrict__ xnext,
                                           const uint16_t* __restrict__ vh_next,
                                           const uint16_t* __restrict__ vl_next) {
   constexpr int DP = (D + 3) & ~3;
   constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
+  constexpr int NV = (MODE == P_BF16X3 ? 6 : 12);
 #pragma unroll
   for (int e = 0; e < 8; ++e) load_point<D>(xnext + e * DP, xn[e]);
-  // half 1: A(rs1, k) on the VALU while acc[rs0] accumulates on the matrix cores
-  bf16x8 a1h, a1l;
-  tile_a<MODE, D>(xi[1], xc, a1h, a1l);
+  // sub-tiles 0..RS-2: A(r+1, k) on the VALU while acc[r] accumulates
+  bf16x8 ah = a0h, al = a0l;
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) mfma3<MODE>(acc[0][ct], a0h, a0l, bh[ct], bl[ct]);
-  __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
-  interleave<NM, (MODE == P_BF16X3 ? 6 : 12)>();
-  __builtin_amdgcn_sched_barrier(0);
-  // half 2: A(rs0, k+1) on the VALU while acc[rs1] accumulates; V tiles refilled
+  for (int r = 0; r + 1 < RS; ++r) {
+    bf16x8 nh, nl;
+    tile_a<MODE, D>(xi[r + 1], xc, nh, nl);
+    mfma_tiles<MODE, CT>(acc[r], ah, al, bh, bl);
+    if (r == 0) __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
+    interleave<NM, NV>();
+    __builtin_amdgcn_sched_barrier(0);
+    ah = nh;
+    al = nl;
+  }
+  // last sub-tile: A(0, k+1) on the VALU while acc[RS-1] accumulates; V refilled
   tile_a<MODE, D>(xi[0], xn, n0h, n0l);
+  if (MODE == P_BF16X3) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[RS - 1][ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[RS - 1][ct], 0, 0, 0);
+      bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
+    }
+  }
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
-    mfma3<MODE>(acc[1][ct], a1h, a1l, bh[ct], bl[ct]);
+    acc[RS - 1][ct] =
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[RS - 1][ct], 0, 0, 0);
     bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
-    if (MODE == P_BF16X3) bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
   }
-  interleave<NM, (MODE == P_BF16X3 ? 6 : 12)>();
+  interleave<NM, NV>();
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int CT>
-__device__ __forceinline__ void epilogue(const f32x4 (&acc)[2][CT], int64_t row0, int l16, int g,
+template <int CT, int RS>
+__device__ __forceinline__ void epilogue(const f32x4 (&acc)[RS][CT], int64_t row0, int l16, int g,
                                          int64_t n1, int64_t n1_pad, int c, int S, int64_t sp,
                                          float* __restrict__ out, int64_t ldo,
                                          float* __restrict__ part, float scale,
                                          const float* __restrict__ vn, int64_t ldv,
                                          float noise) {
 #pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
+  for (int rs = 0; rs < RS; ++rs)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
@@ -203,26 +233,48 @@ __device__ __forceinline__ void epilogue(const f32x4 (&acc)[2][CT], int64_t row0
       }
 }
 
-template <int CT>
-__device__ __forceinline__ void zero(f32x4 (&a)[2][CT]) {
+template <int CT, int RS>
+__device__ __forceinline__ void zero(f32x4 (&a)[RS][CT]) {
 #pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
+  for (int rs = 0; rs < RS; ++rs)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) a[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
-template <int CT>
-__device__ __forceinline__ void fold(f32x4 (&tot)[2][CT], f32x4 (&acc)[2][CT]) {
+// Running totals of the two-level summation live in a wave-private LDS slice
+// ([RS * CT * 4 values][64 lanes], lane-contiguous, so no bank conflicts and no
+// barriers) instead of 4*RS*CT extra VGPRs, which keeps occupancy up.
+template <int CT, int RS>
+__device__ __forceinline__ void fold(float* __restrict__ tl, f32x4 (&acc)[RS][CT], int lane) {
 #pragma unroll
-  for (int rs = 0; rs < 2; ++rs)
+  for (int rs = 0; rs < RS; ++rs)
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      tot[rs][ct] += acc[rs][ct];
-      acc[rs][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        tl[((rs * CT + ct) * 4 + q) * 64 + lane] += acc[rs][ct][q];
+        acc[rs][ct][q] = 0.f;
+      }
 }
 
-template <int MODE, int D, int CT>
+template <int CT, int RS>
+__device__ __forceinline__ void tot_init(float* __restrict__ tl, int lane) {
+#pragma unroll
+  for (int k = 0; k < RS * CT * 4; ++k) tl[k * 64 + lane] = 0.f;
+}
+
+template <int CT, int RS>
+__device__ __forceinline__ void tot_read(const float* __restrict__ tl, f32x4 (&tot)[RS][CT],
+                                         int lane) {
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tot[rs][ct][q] = tl[((rs * CT + ct) * 4 + q) * 64 + lane];
+}
+
+template <int MODE, int D, int CT, int RS>
 __global__ __launch_bounds__(256, 2) void kfwd_bf16(
     const float* __restrict__ xp1, const float* __restrict__ xp2,
     const uint16_t* __restrict__ vhi, const uint16_t* __restrict__ vlo, int64_t n1,
@@ -236,17 +288,19 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
   const int g = lane >> 4;
   const int64_t rb = blockIdx.x / S;
   const int64_t sp = blockIdx.x % S;
-  const int64_t row0 = rb * kFwdRowsPerWG + wave * 32;
+  const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
   const int64_t s0 = steps * sp / S;
   const int64_t s1 = steps * (sp + 1) / S;
 
-  float xi[2][D];
+  float xi[RS][D];
 #pragma unroll
-  for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
+  for (int rs = 0; rs < RS; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
-  f32x4 tot[2][CT], acc[2][CT];
-  zero<CT>(tot);
-  zero<CT>(acc);
+  __shared__ float tot_lds[4][RS * CT * 4 * 64];
+  float* tl = tot_lds[wave];
+  tot_init<CT, RS>(tl, lane);
+  f32x4 acc[RS][CT];
+  zero<CT, RS>(acc);
 
   if (s0 < s1) {
     // per-lane offsets: coordinates of columns 8g..8g+7, V tile element (col l16, rows 8g..)
@@ -269,27 +323,29 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
     int left = kChunk;
     while (true) {
       int64_t nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step<MODE, D, CT>(xi, X0, X1, bh, bl, A0h, A0l, A1h, A1l, acc,
+      bf16_step<MODE, D, CT, RS>(xi, X0, X1, bh, bl, A0h, A0l, A1h, A1l, acc,
                              xb + nx * kJStep * DP, vhi + nx * tstride + voff,
                              vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
-        fold<CT>(tot, acc);
+        fold<CT, RS>(tl, acc, lane);
         left = kChunk;
       }
       nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step<MODE, D, CT>(xi, X1, X0, bh, bl, A1h, A1l, A0h, A0l, acc,
+      bf16_step<MODE, D, CT, RS>(xi, X1, X0, bh, bl, A1h, A1l, A0h, A0l, acc,
                              xb + nx * kJStep * DP, vhi + nx * tstride + voff,
                              vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
-        fold<CT>(tot, acc);
+        fold<CT, RS>(tl, acc, lane);
         left = kChunk;
       }
     }
-    fold<CT>(tot, acc);
+    fold<CT, RS>(tl, acc, lane);
   }
-  epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
+  f32x4 tot[RS][CT];
+  tot_read<CT, RS>(tl, tot, lane);
+  epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
 }
 
 // FP32 pipeline: same structure with 8 scalar A operands per row sub-tile and
@@ -302,32 +358,41 @@ __device__ __forceinline__ void f32_vals(const float (&xi)[D], const float (&xj)
     m[kk] = (FN == FN_MATERN) ? matern_r2(sqdist<D>(xi, xj[kk])) : dlen_val<D>(xi, xj[kk], fd);
 }
 
-template <int D, int CT, int FN>
-__device__ __forceinline__ void f32_step(const float (&xi)[2][D], const float (&xc)[8][D],
+template <int D, int CT, int FN, int RS>
+__device__ __forceinline__ void f32_step(const float (&xi)[RS][D], const float (&xc)[8][D],
                                          float (&xn)[8][D], float (&b)[CT][8],
                                          const float (&a0)[8], float (&n0)[8],
-                                         f32x4 (&acc)[2][CT], int fd,
+                                         f32x4 (&acc)[RS][CT], int fd,
                                          const float* __restrict__ xnext,
                                          const float* __restrict__ vnext) {
   constexpr int DP = (D + 3) & ~3;
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk) load_point<D>(xnext + 4 * kk * DP, xn[kk]);
-  float a1[8];
-  f32_vals<D, FN>(xi[1], xc, fd, a1);
+  float a[8];
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct)
+  for (int kk = 0; kk < 8; ++kk) a[kk] = a0[kk];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk)
-      acc[0][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[kk], b[ct][kk], acc[0][ct], 0, 0, 0);
-  __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
-  interleave<8 * CT, 2>();
-  __builtin_amdgcn_sched_barrier(0);
+  for (int r = 0; r + 1 < RS; ++r) {
+    float nx[8];
+    f32_vals<D, FN>(xi[r + 1], xc, fd, nx);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[r][ct], 0, 0, 0);
+    if (r == 0) __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, 2 * D, 0);
+    interleave<8 * CT, 2>();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = nx[kk];
+  }
   f32_vals<D, FN>(xi[0], xn, fd, n0);
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk)
-      acc[1][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[kk], b[ct][kk], acc[1][ct], 0, 0, 0);
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[RS - 1][ct], 0, 0, 0);
     const float4 lo4 = *reinterpret_cast<const float4*>(vnext + ct * 512);
     const float4 hi4 = *reinterpret_cast<const float4*>(vnext + ct * 512 + 4);
     b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
@@ -337,7 +402,7 @@ __device__ __forceinline__ void f32_step(const float (&xi)[2][D], const float (&
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int D, int CT, int FN>
+template <int D, int CT, int FN, int RS>
 __global__ __launch_bounds__(256, 2) void kfwd_f32(
     const float* __restrict__ xp1, const float* __restrict__ xp2, const float* __restrict__ vf,
     int64_t n1, int64_t n1_pad, int64_t steps, int S, float* __restrict__ out, int64_t ldo,
@@ -350,17 +415,19 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
   const int g = lane >> 4;
   const int64_t rb = blockIdx.x / S;
   const int64_t sp = blockIdx.x % S;
-  const int64_t row0 = rb * kFwdRowsPerWG + wave * 32;
+  const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
   const int64_t s0 = steps * sp / S;
   const int64_t s1 = steps * (sp + 1) / S;
 
-  float xi[2][D];
+  float xi[RS][D];
 #pragma unroll
-  for (int rs = 0; rs < 2; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
+  for (int rs = 0; rs < RS; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
 
-  f32x4 tot[2][CT], acc[2][CT];
-  zero<CT>(tot);
-  zero<CT>(acc);
+  __shared__ float tot_lds[4][RS * CT * 4 * 64];
+  float* tl = tot_lds[wave];
+  tot_init<CT, RS>(tl, lane);
+  f32x4 acc[RS][CT];
+  zero<CT, RS>(acc);
 
   if (s0 < s1) {
     // per-lane offsets: columns g + 4 kk, V tile element (col l16, rows g + 4 kk)
@@ -385,44 +452,49 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
     int left = kChunk;
     while (true) {
       int64_t nx = st + 1 < s1 ? st + 1 : st;
-      f32_step<D, CT, FN>(xi, X0, X1, b, A0, A1, acc, fn_dim, xb + nx * kJStep * DP,
-                          vf + nx * tstride + voff);
+      f32_step<D, CT, FN, RS>(xi, X0, X1, b, A0, A1, acc, fn_dim, xb + nx * kJStep * DP,
+                              vf + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
-        fold<CT>(tot, acc);
+        fold<CT, RS>(tl, acc, lane);
         left = kChunk;
       }
       nx = st + 1 < s1 ? st + 1 : st;
-      f32_step<D, CT, FN>(xi, X1, X0, b, A1, A0, acc, fn_dim, xb + nx * kJStep * DP,
-                          vf + nx * tstride + voff);
+      f32_step<D, CT, FN, RS>(xi, X1, X0, b, A1, A0, acc, fn_dim, xb + nx * kJStep * DP,
+                              vf + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
-        fold<CT>(tot, acc);
+        fold<CT, RS>(tl, acc, lane);
         left = kChunk;
       }
     }
-    fold<CT>(tot, acc);
+    fold<CT, RS>(tl, acc, lane);
   }
-  epilogue<CT>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
+  f32x4 tot[RS][CT];
+  tot_read<CT, RS>(tl, tot, lane);
+  epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv,
+                   noise);
 }
 
 template <int D, int CT>
 hipError_t launch(const FwdArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)(a.n1_pad / kFwdRowsPerWG * a.S));
+  constexpr int RS = fwd_row_subtiles(CT);
+  if (a.n1_pad % (64 * RS)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(a.n1_pad / (64 * RS) * a.S));
   if (a.prec == P_BF16X3) {
-    hipLaunchKernelGGL((kfwd_bf16<P_BF16X3, D, CT>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+    hipLaunchKernelGGL((kfwd_bf16<P_BF16X3, D, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad, a.steps,
                        a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
   } else if (a.prec == P_BF16) {
-    hipLaunchKernelGGL((kfwd_bf16<P_BF16, D, CT>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+    hipLaunchKernelGGL((kfwd_bf16<P_BF16, D, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1, a.n1_pad, a.steps,
                        a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
   } else if (a.fn == FN_MATERN) {
-    hipLaunchKernelGGL((kfwd_f32<D, CT, FN_MATERN>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+    hipLaunchKernelGGL((kfwd_f32<D, CT, FN_MATERN, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,
                        a.part, a.scale, a.vn, a.ldv, a.noise, a.fn_dim);
   } else {
-    hipLaunchKernelGGL((kfwd_f32<D, CT, FN_DLEN>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+    hipLaunchKernelGGL((kfwd_f32<D, CT, FN_DLEN, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,
                        a.part, a.scale, a.vn, a.ldv, a.noise, a.fn_dim);
   }

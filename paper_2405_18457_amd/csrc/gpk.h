@@ -21,10 +21,13 @@ constexpr float kLn2 = 0.693147180559945309f;
 // Every packed row array is padded with zero rows to a multiple of this, so
 // that kernels need no bounds checks on the j (column) stream and every
 // workgroup's rows are addressable.
-constexpr int kRowAlign = 128;
+constexpr int kRowAlign = 256;
 constexpr int kJStep = 32;          // forward kernel: kernel columns per MFMA K-chunk
-constexpr int kFwdRowsPerWG = 128;  // 4 waves x 2 row sub-tiles x 16 rows
 constexpr int kAdjRowsPerWG = 128;
+// Row sub-tiles of 16 rows per wave in the forward kernel (4 waves per
+// workgroup): 4 for up to 5 column tiles (80 columns), 2 for wider products.
+constexpr int fwd_row_subtiles(int CT) { return CT <= 5 ? 4 : 2; }
+inline int fwd_rows_per_wg(int CT) { return 64 * fwd_row_subtiles(CT); }
 constexpr int kMaxD = 64;
 constexpr int kMaxC = 256;
 

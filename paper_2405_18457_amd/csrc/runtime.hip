@@ -244,7 +244,7 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
       a.vhi = hi;
       a.vlo = lo;
     }
-    const int64_t rowblocks = p1.n_pad / kFwdRowsPerWG;
+    const int64_t rowblocks = p1.n_pad / fwd_rows_per_wg(CT);
     a.S = choose_splits(rowblocks, a.steps);
     if (a.S > 1) CHK(ensure(ctx, B_PART, (size_t)(a.S * p1.n_pad * 16 * CT), &a.part));
     {
