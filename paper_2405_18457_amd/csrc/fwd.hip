@@ -348,6 +348,177 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
   epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv, noise);
 }
 
+// ---------------------------------------------------------------------------
+// Cross-term path (bf16 modes, d <= 3).  Points are packed as
+// [x^_0, x^_1, x^_2, |x^|^2]; with A'[j] = [-2 x^_j, |x^_j|^2] and
+// B'[i] = [x^_i, 1] one v_mfma_f32_16x16x4_f32 gives |x^_j|^2 - 2 x^_i.x^_j for a
+// 16 x 16 block and r^2 = that + |x^_i|^2, i.e. 2 VALU ops per kernel entry
+// instead of 2d on the direct path, and one scalar column load per lane and
+// half-step instead of eight points.  The product's output layout gives each
+// lane rows j = 4g..4g+3 (and 16 + 4g..) of one column i, so the V tiles are
+// packed with the matching row permutation (xt_k_of_j in vec.hip).  The FP32
+// cancellation error in r^2 grows with |x^|^2; the library uses this path only
+// when max |x^|^2 <= kXTMaxNorm2 and otherwise the direct path.
+template <int MODE>
+__device__ __forceinline__ void tile_a_xt(float bx, float ni, float ajl, float ajh, bf16x8& ah,
+                                          bf16x8& al) {
+  // |x^_i|^2 enters as the accumulator input; a slightly negative r^2 left by
+  // cancellation is taken by magnitude (a free source modifier), which perturbs
+  // m by the same O(|r^2 error|) as clamping at zero would
+  const f32x4 c = {ni, ni, ni, ni};
+  const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajl, bx, c, 0, 0, 0);
+  const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajh, bx, c, 0, 0, 0);
+  float r2[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    r2[q] = __builtin_fabsf(d0[q]);
+    r2[4 + q] = __builtin_fabsf(d1[q]);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const float m0 = matern_r2(r2[e]);
+    const float m1 = matern_r2(r2[e + 1]);
+    const bf16x2 h = __builtin_convertvector((f32x2){m0, m1}, bf16x2);
+    ah[e] = h[0];
+    ah[e + 1] = h[1];
+    if (MODE == P_BF16X3) {
+      const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+      const float h0 = __builtin_bit_cast(float, hb << 16);
+      const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+      const bf16x2 l = __builtin_convertvector((f32x2){m0 - h0, m1 - h1}, bf16x2);
+      al[e] = l[0];
+      al[e + 1] = l[1];
+    }
+  }
+}
+
+template <int MODE, int CT, int RS>
+__device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS], const float (&ni)[RS],
+                                             float ajl, float ajh, float& njl, float& njh,
+                                             bf16x8 (&bh)[CT], bf16x8 (&bl)[CT],
+                                             const bf16x8& a0h, const bf16x8& a0l, bf16x8& n0h,
+                                             bf16x8& n0l, f32x4 (&acc)[RS][CT],
+                                             const float* __restrict__ xnext, float mult,
+                                             const uint16_t* __restrict__ vh_next,
+                                             const uint16_t* __restrict__ vl_next) {
+  constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
+  const float rl = xnext[0];
+  const float rh = xnext[16 * 4];
+  bf16x8 ah = a0h, al = a0l;
+#pragma unroll
+  for (int r = 0; r + 1 < RS; ++r) {
+    bf16x8 nh, nl;
+    tile_a_xt<MODE>(bx[r + 1], ni[r + 1], ajl, ajh, nh, nl);
+    mfma_tiles<MODE, CT>(acc[r], ah, al, bh, bl);
+    interleave<NM + 2, 4>();
+    __builtin_amdgcn_sched_barrier(0);
+    ah = nh;
+    al = nl;
+  }
+  njl = rl * mult;
+  njh = rh * mult;
+  tile_a_xt<MODE>(bx[0], ni[0], njl, njh, n0h, n0l);
+  if (MODE == P_BF16X3) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[RS - 1][ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[RS - 1][ct], 0, 0, 0);
+      bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    acc[RS - 1][ct] =
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[RS - 1][ct], 0, 0, 0);
+    bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
+  }
+  interleave<NM + 2, 4>();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int MODE, int CT, int RS>
+__global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
+    const float* __restrict__ xp1, const float* __restrict__ xp2,
+    const uint16_t* __restrict__ vhi, const uint16_t* __restrict__ vlo, int64_t n1,
+    int64_t n1_pad, int64_t steps, int S, float* __restrict__ out, int64_t ldo, int c,
+    float* __restrict__ part, float scale, const float* __restrict__ vn, int64_t ldv,
+    float noise) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int g = lane >> 4;
+  const int64_t rb = blockIdx.x / S;
+  const int64_t sp = blockIdx.x % S;
+  const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
+  const int64_t s0 = steps * sp / S;
+  const int64_t s1 = steps * (sp + 1) / S;
+
+  // B' operand (k = g) and |x^_i|^2 of this lane's row in every sub-tile
+  float bx[RS], ni[RS];
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) {
+    const float* pi = xp1 + (row0 + rs * 16 + l16) * 4;
+    bx[rs] = g == 3 ? 1.f : pi[g];
+    ni[rs] = pi[3];
+  }
+  const float mult = g == 3 ? 1.f : -2.f;  // A'[j][g] = mult * packed[j][g]
+
+  __shared__ float tot_lds[4][RS * CT * 4 * 64];
+  float* tl = tot_lds[wave];
+  tot_init<CT, RS>(tl, lane);
+  f32x4 acc[RS][CT];
+  zero<CT, RS>(acc);
+
+  if (s0 < s1) {
+    const float* xb = xp2 + l16 * 4 + g;  // column j = 32 st + l16 (+16), coordinate g
+    const int64_t voff = l16 * 32 + 8 * g;
+    const int64_t tstride = (int64_t)CT * 512;
+    float J0l, J0h, J1l, J1h;
+    bf16x8 bh[CT], bl[CT];
+    bf16x8 A0h, A0l, A1h, A1l;
+    J0l = xb[s0 * kJStep * 4] * mult;
+    J0h = xb[(s0 * kJStep + 16) * 4] * mult;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      bh[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
+      if (MODE == P_BF16X3)
+        bl[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
+    }
+    tile_a_xt<MODE>(bx[0], ni[0], J0l, J0h, A0h, A0l);
+    int64_t st = s0;
+    int left = kChunk;
+    while (true) {
+      int64_t nx = st + 1 < s1 ? st + 1 : st;
+      bf16_step_xt<MODE, CT, RS>(bx, ni, J0l, J0h, J1l, J1h, bh, bl, A0h, A0l, A1h, A1l, acc,
+                                 xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
+                                 vlo + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT, RS>(tl, acc, lane);
+        left = kChunk;
+      }
+      nx = st + 1 < s1 ? st + 1 : st;
+      bf16_step_xt<MODE, CT, RS>(bx, ni, J1l, J1h, J0l, J0h, bh, bl, A1h, A1l, A0h, A0l, acc,
+                                 xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
+                                 vlo + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT, RS>(tl, acc, lane);
+        left = kChunk;
+      }
+    }
+    fold<CT, RS>(tl, acc, lane);
+  }
+  f32x4 tot[RS][CT];
+  tot_read<CT, RS>(tl, tot, lane);
+  epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv,
+                   noise);
+}
+
 // FP32 pipeline: same structure with 8 scalar A operands per row sub-tile and
 // 8 K=4 MFMAs per 16-column tile per step.
 template <int D, int FN>
@@ -481,6 +652,20 @@ hipError_t launch(const FwdArgs& a, hipStream_t st) {
   constexpr int RS = fwd_row_subtiles(CT);
   if (a.n1_pad % (64 * RS)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(a.n1_pad / (64 * RS) * a.S));
+  if constexpr (D <= 3) {
+    if (a.xt && a.prec == P_BF16X3) {
+      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16X3, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+                         (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad,
+                         a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
+      return hipGetLastError();
+    }
+    if (a.xt && a.prec == P_BF16) {
+      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
+                         (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1, a.n1_pad,
+                         a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
+      return hipGetLastError();
+    }
+  }
   if (a.prec == P_BF16X3) {
     hipLaunchKernelGGL((kfwd_bf16<P_BF16X3, D, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad, a.steps,

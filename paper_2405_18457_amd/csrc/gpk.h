@@ -54,9 +54,17 @@ hipError_t pack_x(const float* X, int64_t n, int d, int DP, const DimScale& sc, 
                   int64_t n_pad, hipStream_t st);
 hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, int DP,
                        const DimScale& sc, float* Xp, int64_t n_pad, hipStream_t st);
-// V [n, ldv] (first c columns, optional per-column scale) into forward tiles.
+// d <= 3: rows [x^_0, x^_1, x^_2, |x^|^2]; atomically records max |x^|^2 (float bits).
+hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, const DimScale& sc,
+                      float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st);
+// Largest |x^|^2 for which the cross-term path is used: its FP32 cancellation
+// error in r^2 then stays near 1e-4 absolute (about 1e-5 relative in a product).
+constexpr float kXTMaxNorm2 = 1024.f;
+// V [n, ldv] (first c columns, optional per-column scale) into forward tiles;
+// perm = the row order of the cross-term path (see fwd.hip).
 hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
-                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st);
+                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, bool perm,
+                       hipStream_t st);
 hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
                       int CT, float* out, int64_t n_pad, hipStream_t st);
 // Row-major [n_pad, 32*KT] packs for the adjoint (optional per-column weights).
@@ -87,6 +95,7 @@ struct FwdArgs {
   const float* vn = nullptr;       // [n1, ldv] or null
   int64_t ldv = 0;
   float noise = 0.f;
+  int xt = 0;                      // bf16 modes, D <= 3: distances from the MFMA cross term
 };
 hipError_t fwd(const FwdArgs& a, hipStream_t st);
 // Sum of the S partial products plus the epilogue (used when S > 1).

@@ -25,7 +25,7 @@ namespace {
 enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
-  B_WB, B_IDX, B_GX, B_G, B_APF, B_COUNT
+  B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -36,6 +36,7 @@ struct Packed {
   float* xp = nullptr;
   int64_t n = 0, n_pad = 0;
   int D = 0, DP = 0;
+  bool xt_ok = false;  // |x^|^2 stored in slot 3 and small enough for the cross-term path
 };
 
 }  // namespace
@@ -198,10 +199,27 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
   DimScale sc{};
   for (int k = 0; k < d; ++k) sc.s[k] = (float)(kSqrt3Log2e / theta[k]);
   CHK(ensure(ctx, id, (size_t)(p->n_pad * p->DP), &p->xp));
-  if (idx)
+  p->xt_ok = false;
+  if (p->D <= 3) {
+    // squared norms ride in the padding slot; their maximum decides whether the
+    // cross-term distance form is accurate enough for these points
+    unsigned* mx;
+    CHK(ensure(ctx, B_XTMAX, 1, &mx));
+    CHK(ensure_pinned(ctx, 1));
+    HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), ctx->stream));
+    HIPCHK(pack_x_aug(X, idx, n, d, sc, p->xp, p->n_pad, mx, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->hpin, mx, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    unsigned bits;
+    std::memcpy(&bits, ctx->hpin, sizeof(unsigned));
+    float m;
+    std::memcpy(&m, &bits, sizeof(float));
+    p->xt_ok = std::isfinite(m) && m <= kXTMaxNorm2;
+  } else if (idx) {
     HIPCHK(pack_x_rows(X, idx, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
-  else
+  } else {
     HIPCHK(pack_x(X, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+  }
   return GP_OK;
 }
 
@@ -230,6 +248,7 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     a.vn = vn ? vn + c0 : nullptr;
     a.ldv = ldvn;
     a.noise = noise;
+    a.xt = prec != GP_FP32 && fn == FN_MATERN && p1.xt_ok && p2.xt_ok;
     const size_t vcount = (size_t)(p2.n_pad * 16 * CT);
     if (prec == GP_FP32) {
       float* vf;
@@ -240,7 +259,8 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
       uint16_t *hi, *lo = nullptr;
       CHK(ensure(ctx, B_VHI, vcount, &hi));
       if (prec == GP_BF16X3) CHK(ensure(ctx, B_VLO, vcount, &lo));
-      HIPCHK(pack_v_bf16(V + c0, p2.n, ldv, cs, nullptr, CT, hi, lo, p2.n_pad, ctx->stream));
+      HIPCHK(pack_v_bf16(V + c0, p2.n, ldv, cs, nullptr, CT, hi, lo, p2.n_pad, a.xt != 0,
+                         ctx->stream));
       a.vhi = hi;
       a.vlo = lo;
     }

@@ -34,10 +34,34 @@ __global__ void kpack_x(const float* __restrict__ X, const int32_t* __restrict__
   Xp[t] = v;
 }
 
+// Points with d <= 3 packed as [x^_0, x^_1, x^_2, |x^|^2] (unused coordinates 0);
+// the largest |x^|^2 is recorded (float bits, non-negative) for the caller.
+__global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restrict__ idx,
+                            int64_t n, int d, DimScale sc, float4* __restrict__ Xp,
+                            int64_t n_pad, unsigned* __restrict__ maxbits) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n_pad) return;
+  float v[3] = {0.f, 0.f, 0.f};
+  if (i < n) {
+    const int64_t src = idx ? (int64_t)idx[i] : i;
+    for (int k = 0; k < d; ++k) v[k] = X[src * d + k] * sc.s[k];
+  }
+  const float nn = __builtin_fmaf(v[0], v[0], __builtin_fmaf(v[1], v[1], v[2] * v[2]));
+  Xp[i] = make_float4(v[0], v[1], v[2], nn);
+  if (maxbits && i < n) atomicMax(maxbits, __builtin_bit_cast(unsigned, nn));
+}
+
+// Position of row j (within a 32-row tile) on the MFMA contraction index when the
+// kernel tile comes from two 16x16x4 cross-term products (rows 4g..4g+3 and
+// 16+4g..16+4g+3 of lane group g feed k = 8g..8g+7).
+__device__ __forceinline__ int xt_k_of_j(int j) {
+  return 8 * ((j & 15) >> 2) + (j & 3) + 4 * (j >> 4);
+}
+
 __global__ void kpack_v_bf16(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
                              const float* __restrict__ colscale, int CT,
                              uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
-                             int64_t n_pad) {
+                             int64_t n_pad, int perm) {
   const int CP = 16 * CT;
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= n_pad * CP) return;
@@ -45,7 +69,8 @@ __global__ void kpack_v_bf16(const float* __restrict__ V, int64_t n, int64_t ldv
   const int col = (int)(t % CP);
   float v = 0.f;
   if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
-  const int64_t off = ((j / 32) * CT + col / 16) * 512 + (col % 16) * 32 + (j % 32);
+  const int jk = perm ? xt_k_of_j((int)(j % 32)) : (int)(j % 32);
+  const int64_t off = ((j / 32) * CT + col / 16) * 512 + (col % 16) * 32 + jk;
   const uint16_t h = bf16_bits(v);
   hi[off] = h;
   if (lo) lo[off] = bf16_bits(v - bf16_val(h));
@@ -368,10 +393,18 @@ hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, 
   return hipGetLastError();
 }
 
+hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, const DimScale& sc,
+                      float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st) {
+  hipLaunchKernelGGL(kpack_x_aug, dim3(blocks_for(n_pad)), dim3(kThreads), 0, st, X, idx, n, d, sc,
+                     reinterpret_cast<float4*>(Xp), n_pad, maxbits);
+  return hipGetLastError();
+}
+
 hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
-                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st) {
+                       int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, bool perm,
+                       hipStream_t st) {
   hipLaunchKernelGGL(kpack_v_bf16, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V,
-                     n, ldv, c, colscale, CT, hi, lo, n_pad);
+                     n, ldv, c, colscale, CT, hi, lo, n_pad, (int)perm);
   return hipGetLastError();
 }
 

@@ -125,3 +125,30 @@ def test_full_size_precision_workload_sampled_rows(gp, prec):
     ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
     err = col_relerr(out[rows], ref)
     assert err <= TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16x3", "bf16"])
+@pytest.mark.parametrize("shift_rows,shift_cols", [(0.0, 0.0), (40.0, 40.0), (0.0, 40.0)])
+def test_low_dimension_distance_forms(gp, prec, shift_rows, shift_cols):
+    """For d <= 3 the bf16 products take squared distances from the norm expansion
+    on the matrix cores when every scaled point has |x^|^2 <= 1024 and from direct
+    differences otherwise; both forms meet the same bound."""
+    from paper_2405_18457_amd import api
+    X, V, theta = problem(1100, 3, 33, seed=77, dist="uniform", ell_scale=(0.15, 0.25))
+    Q, _, _ = problem(413, 3, 1, seed=78, dist="uniform")
+    # a few far-away points (their kernel values vanish) push the set's maximum norm
+    # past the cross-term limit while the rest of the product stays non-trivial
+    X[-50:] += np.float32(shift_cols)
+    Q[-20:] += np.float32(shift_rows)
+    scale = np.sqrt(3.0) / np.log(2.0) / theta[:3]
+    for P, shift in ((Q, shift_rows), (X, shift_cols)):
+        big = float(((P.astype(np.float64) * scale) ** 2).sum(1).max())
+        assert (big > 1024.0) == (shift > 0.0), big
+    announce("kmatvec-xt", prec, shift_rows, shift_cols)
+    out = host(api.gp_kmatvec(gp, dev(Q), dev(X), theta, dev(V), precision=prec))
+    ref = kernel.k_matvec(Q, X, theta, V)
+    if prec == 2:
+        err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    else:
+        err = col_relerr(out, ref)
+    assert err <= TOL[prec], err
