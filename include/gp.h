@@ -90,8 +90,10 @@ const char* gp_version(void);
  * enable != 0 starts recording (and clears totals); enable = 0 stops.
  * gp_profile_read synchronises the stream and returns the summed duration in
  * milliseconds and the launch count of kernel class `which`:
- *   0 = forward product in GP_BF16X3 / GP_BF16, 1 = fused adjoint,
- *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product in GP_FP32.
+ *   0 = forward product kernel in GP_BF16X3 / GP_BF16, 1 = fused adjoint,
+ *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product kernel
+ *   in GP_FP32 (classes 0 and 4 time the product kernel alone, not the sum of
+ *   its column-split partials).
  * Errors: GP_ERR_INVALID_ARG for an unknown class.                          */
 int gp_profile_enable(gp_ctx* ctx, int enable);
 int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);
