@@ -21,6 +21,7 @@ Processes", NeurIPS 2024) in float64, slow and obvious:
               "Kernel Function and Random Features").
   solvers  -- conjugate gradients, alternating projections, SGD (App. B,
               Algorithms 1-3) with the relative-residual stopping rule.
+  precond  -- the rank-k pivoted Cholesky preconditioner of CG (App. B).
   optim    -- softplus / log reparameterisation and Adam (App. B "Iterative
               Optimiser").
 
@@ -29,6 +30,6 @@ Parity status: every function has at least one independent pin in
 *selection order* (any argmax rule gives a valid AP; the paper's code is not
 available), which is marked "parity unpinned" in ``solvers.ap``.
 """
-from . import kernel, mll, rff, solvers, optim, train  # noqa: F401
+from . import kernel, mll, rff, solvers, optim, train, precond  # noqa: F401
 
-__all__ = ["kernel", "mll", "rff", "solvers", "optim", "train"]
+__all__ = ["kernel", "mll", "rff", "solvers", "optim", "train", "precond"]

@@ -13,9 +13,12 @@ Written from App. B ("Linear System Solver", Algorithms 1-3).  Common rules:
 * Budget: T epochs.  One CG iteration is one epoch; AP and SGD run while
   t < (n/b) T (a real comparison), i.e. ceil(nT/b) iterations.  T=None means
   tolerance only, with a safety cap.
-* CG preconditioner: the paper uses rank-100 pivoted Cholesky; this oracle
-  (like the GPU path) uses P = I.  Columns run in parallel with their own
-  alpha/beta; a column whose gamma is exactly 0 is frozen (alpha = beta = 0).
+* CG preconditioner: Algorithm 1's P(.) applies the inverse of a
+  preconditioner matrix (``precond``: a callable R -> P^-1 R, e.g.
+  ``oracle.precond.preconditioner``; the paper's experiments use a rank-100
+  pivoted Cholesky factor); ``precond=None`` is P = I.  Columns run in
+  parallel with their own alpha/beta; a column whose gamma is exactly 0 is
+  frozen (alpha = beta = 0).
 
 Statuses: ``SolverError`` with code "nonfinite" (NaN/Inf residual) or
 "breakdown" (d^T H d <= 0 on a live column).
@@ -101,13 +104,15 @@ def _normalise(B, U0):
     return Bt, V, scale
 
 
-def cg(op, B, tol=0.01, max_epochs=None, U0=None):
-    """Algorithm 1 (P = I).  Returns (U, stats)."""
+def cg(op, B, tol=0.01, max_epochs=None, U0=None, precond=None):
+    """Algorithm 1.  Returns (U, stats)."""
+    Pinv = (lambda R: R) if precond is None else precond
     Bt, V, scale = _normalise(B, U0)
     R = Bt - op.matvec(V)
     matvecs = 1
-    D = R.copy()
-    gamma = np.einsum("ic,ic->c", R, R)
+    Z = Pinv(R)
+    D = Z.copy()
+    gamma = np.einsum("ic,ic->c", R, Z)
     t = 0
     cap = SAFETY_CAP if max_epochs is None else max_epochs
     ry, rz = relres(R)
@@ -122,10 +127,11 @@ def cg(op, B, tol=0.01, max_epochs=None, U0=None):
         alpha = np.where(live, gamma / np.where(live, dHd, 1.0), 0.0)
         V = V + alpha * D
         R = R - alpha * HD
-        gnew = np.einsum("ic,ic->c", R, R)
+        Z = Pinv(R)
+        gnew = np.einsum("ic,ic->c", R, Z)
         beta = np.where(live, gnew / np.where(live, gamma, 1.0), 0.0)
         gamma = gnew
-        D = R + beta * D
+        D = Z + beta * D
         t += 1
         _check_finite(R)
         ry, rz = relres(R)
