@@ -66,6 +66,9 @@ def parse():
                          "(65 columns, same launch configuration); for profilers")
     ap.add_argument("--precision", choices=["bf16x3", "fp32", "bf16"], default="bf16x3",
                     help="product precision for --kernel-only")
+    ap.add_argument("--precond-rank", type=int, default=100,
+                    help="rank of CG's pivoted-Cholesky preconditioner (the paper's setting: 100; "
+                         "0 = none)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler against a known traffic)")
@@ -137,12 +140,12 @@ def build_targets(ctx, inp, tr, dev):
     return y
 
 
-def run_form(ctx, inp, y, form, steps, warmup):
+def run_form(ctx, inp, y, form, steps, warmup, precond_rank):
     import torch
     from paper_2405_18457_amd import api
     prec = api.GP_BF16X3 if form == "bf16x3+adjoint" else api.GP_FP32
     mode = api.GP_ADJ_FUSED if form == "bf16x3+adjoint" else api.GP_ADJ_PER_PARAM
-    cfg = api.solver_cfg(solver=api.GP_CG, tol=1e-2, precision=prec)
+    cfg = api.solver_cfg(solver=api.GP_CG, tol=1e-2, precision=prec, precond_rank=precond_rank)
     tr = api.Trainer(ctx, inp["X"], y, inp["theta_true"], api.GP_PATHWISE, cfg, lr=0.03,
                      s=inp["w"].s, transform=api.GP_SOFTPLUS, warm=True, rff_t=inp["t"],
                      rff_W=inp["W"], w_eps=inp["w_eps"], adjoint_mode=mode)
@@ -163,13 +166,14 @@ def run_form(ctx, inp, y, form, steps, warmup):
         print(f"[bench] {form} step {k}: {log[-1]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = {k: ctx.profile_read(k) for k in range(5)}
+    prof = {k: ctx.profile_read(k) for k in range(6)}
     ctx.profile_enable(False)
     return elapsed, log, prof, tr
 
 
 def _brief(st):
     return {"iters": st["iterations"], "matvecs": st["matvecs"], "refine": st["refinements"],
+            "precond_rank": st["precond_rank"],
             "relres_y": round(st["true_relres_y"], 5) if st["true_relres_y"] == st["true_relres_y"]
             else round(st["relres_y"], 5),
             "relres_z": round(st["true_relres_z"], 5) if st["true_relres_z"] == st["true_relres_z"]
@@ -266,7 +270,8 @@ def main():
     torch.cuda.synchronize()
     n, d, s = inp["n"], inp["w"].d, inp["w"].s
 
-    elapsed, log, prof, trainer = run_form(ctx, inp, y, args.form, args.steps, args.warmup)
+    elapsed, log, prof, trainer = run_form(ctx, inp, y, args.form, args.steps, args.warmup,
+                                           args.precond_rank)
     value = args.steps / elapsed
     timed = [r for r in log if r["phase"] == "timed"]
     iters = float(np.mean([r["iters"] for r in timed])) if timed else 0.0
@@ -279,16 +284,19 @@ def main():
         "config": {"workload": f"precision workload: n={n}, d={d}, x~U[-1,1]^3, ell~U[0.05,0.2], "
                                f"sigma=0.05, s={s}, pathwise + warm start, CG to rel-res 1e-2, "
                                "Adam lr 0.03, theta0 = data-generating theta",
-                   "form": args.form, "n": n, "d": d, "s": s, "solver": "cg", "tol": 1e-2},
+                   "form": args.form, "n": n, "d": d, "s": s, "solver": "cg", "tol": 1e-2,
+                   "precond": f"pivoted Cholesky rank {args.precond_rank}" if args.precond_rank
+                   else "none"},
         "per_step": timed,
         "warmup_log": [r for r in log if r["phase"] == "warmup"],
     }
     if args.form == "bf16x3+adjoint":
         rec["roofline"] = roofline(n, d, s + 1, prof)
     rec["kernel_ms"] = {"fwd_bf16": prof[0], "adjoint": prof[1], "rff": prof[2], "cg_vec": prof[3],
-                        "fwd_fp32": prof[4]}
+                        "fwd_fp32": prof[4], "precond": prof[5]}
     if args.compare:
-        e2, log2, prof2, _ = run_form(ctx, inp, y, "fp32-plain", args.steps, args.warmup)
+        e2, log2, prof2, _ = run_form(ctx, inp, y, "fp32-plain", args.steps, args.warmup,
+                                      args.precond_rank)
         rec["fp32_plain"] = {"value": round(args.steps / e2, 6), "unit": "steps/s",
                              "per_step": [r for r in log2 if r["phase"] == "timed"],
                              "kernel_ms": {"fwd_fp32": prof2[4]}}

@@ -93,7 +93,7 @@ const char* gp_version(void);
  *   0 = forward product kernel in GP_BF16X3 / GP_BF16, 1 = fused adjoint,
  *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product kernel
  *   in GP_FP32 (classes 0 and 4 time the product kernel alone, not the sum of
- *   its column-split partials).
+ *   its column-split partials), 5 = CG preconditioner (construction and apply).
  * Errors: GP_ERR_INVALID_ARG for an unknown class.                          */
 int gp_profile_enable(gp_ctx* ctx, int enable);
 int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);
@@ -145,6 +145,9 @@ typedef struct gp_solver_cfg {
                                  iteration, or NULL to draw them from sgd_seed           */
   int64_t sgd_batches_count;
   uint64_t sgd_seed;
+  int precond_rank;     /* CG only: rank k of the pivoted-Cholesky preconditioner
+                           P = L L^T + sigma^2 I (App. B uses 100); 0 = none (P = I);
+                           at most 2016 and capped at n                             */
 } gp_solver_cfg;
 
 typedef struct gp_solve_stats {
@@ -158,10 +161,13 @@ typedef struct gp_solve_stats {
   double true_relres_z;
   int converged;        /* 1 if both residual norms reached tol                         */
   int status;           /* gp_status of the solve                                        */
+  int precond_rank;     /* rank of the preconditioner actually built (may be below the
+                           requested rank when K is numerically of lower rank)          */
 } gp_solve_stats;
 
 /* Fill *cfg with the paper's defaults: CG, tol 0.01, no budget, FP32,
- * refine_every 0, AP block 1000, SGD batch 500, lr 10, momentum 0.9.        */
+ * refine_every 0, AP block 1000, SGD batch 500, lr 10, momentum 0.9, no
+ * preconditioner (set precond_rank = 100 for the paper's CG configuration).  */
 void gp_solver_cfg_default(gp_solver_cfg* cfg);
 
 /* Solve H [u_0..u_{c-1}] = [b_0..b_{c-1}] (App. B, Algorithms 1-3).
@@ -177,6 +183,20 @@ void gp_solver_cfg_default(gp_solver_cfg* cfg);
 int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
              const float* B, int64_t ldb, float* U, int64_t ldu, int c,
              const gp_solver_cfg* cfg, gp_solve_stats* stats);
+
+/* Rank-k greedy pivoted Cholesky of K(X, X) (the CG preconditioner of App. B):
+ * at step j the pivot p is the row with the largest remaining diagonal (lowest
+ * index on ties), L[:, j] = (K[:, p] - L[:, :j] L[p, :j]^T) / sqrt(d_p) and
+ * d <- d - L[:, j]^2; it stops early when no remaining diagonal is positive.
+ * Kernel columns are evaluated in FP64 from X; the factor is FP64.
+ *   L   DEVICE [k, ldl] doubles, stored transposed: L[j * ldl + i] is entry i
+ *       of factor column j (ldl >= n); entries of rows >= rank are untouched
+ *   piv DEVICE [k] int32 pivot indices (first *rank written)
+ *   rank HOST out: the rank reached (<= min(k, n))
+ * k = 0 or n = 0 is a no-op with *rank = 0.
+ * Errors: GP_ERR_INVALID_ARG (k > 2016, ldl < n, NULL pointers), GP_ERR_HIP. */
+int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
+                        int k, double* L, int64_t ldl, int32_t* piv, int* rank);
 
 /* --------------------------------------------------------- random features */
 

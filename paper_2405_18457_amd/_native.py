@@ -27,7 +27,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_profile_enable",
     "gp_profile_read", "gp_kmatvec", "gp_kmatvec_adjoint", "gp_solver_cfg_default", "gp_solve",
-    "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta",
+    "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_pivoted_cholesky",
 )
 
 
@@ -37,7 +37,7 @@ class SolverCfg(C.Structure):
         ("precision", C.c_int), ("refine_every", C.c_int), ("check_every", C.c_int),
         ("ap_block", C.c_int), ("sgd_batch", C.c_int), ("sgd_lr", C.c_double),
         ("sgd_momentum", C.c_double), ("sgd_batches", C.POINTER(C.c_int32)),
-        ("sgd_batches_count", C.c_int64), ("sgd_seed", C.c_uint64),
+        ("sgd_batches_count", C.c_int64), ("sgd_seed", C.c_uint64), ("precond_rank", C.c_int),
     ]
 
 
@@ -46,7 +46,7 @@ class SolveStats(C.Structure):
         ("iterations", C.c_int64), ("epochs", C.c_double), ("matvecs", C.c_int64),
         ("refinements", C.c_int64), ("relres_y", C.c_double), ("relres_z", C.c_double),
         ("true_relres_y", C.c_double), ("true_relres_z", C.c_double), ("converged", C.c_int),
-        ("status", C.c_int),
+        ("status", C.c_int), ("precond_rank", C.c_int),
     ]
 
     def as_dict(self):
@@ -86,6 +86,8 @@ def lib():
                                   C.POINTER(SolveStats)]),
             "gp_adam_ascent": (i32, [i32, pd, pd, pd, pi64, pd, dbl, i32]),
             "gp_nu_to_theta": (i32, [i32, pd, i32, pd]),
+            "gp_pivoted_cholesky": (i32, [vp, vp, i64, i32, pd, i32, vp, i64, vp,
+                                          C.POINTER(C.c_int)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

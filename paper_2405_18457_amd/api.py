@@ -99,13 +99,14 @@ def _cols(t):
 
 def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine_every=0,
                check_every=0, ap_block=1000, sgd_batch=500, sgd_lr=10.0, sgd_momentum=0.9,
-               sgd_batches: np.ndarray | None = None, sgd_seed=0) -> SolverCfg:
+               sgd_batches: np.ndarray | None = None, sgd_seed=0, precond_rank=0) -> SolverCfg:
     cfg = SolverCfg()
     N.lib().gp_solver_cfg_default(C.byref(cfg))
     cfg.solver, cfg.tol, cfg.max_epochs = solver, tol, max_epochs
     cfg.precision, cfg.refine_every, cfg.check_every = precision, refine_every, check_every
     cfg.ap_block, cfg.sgd_batch, cfg.sgd_lr, cfg.sgd_momentum = ap_block, sgd_batch, sgd_lr, sgd_momentum
     cfg.sgd_seed = sgd_seed
+    cfg.precond_rank = precond_rank
     if sgd_batches is not None:
         arr = np.ascontiguousarray(sgd_batches, dtype=np.int32)
         cfg._batches_keepalive = arr
@@ -158,6 +159,20 @@ def gp_solve(ctx: Context, X, theta, B, U, cfg: SolverCfg):
     ctx.check(N.lib().gp_solve(ctx.handle, x, n, d, thp, b, ldb, u, ldu, c, C.byref(cfg),
                                C.byref(st)))
     return st.as_dict()
+
+
+def gp_pivoted_cholesky(ctx: Context, X, theta, k):
+    """Rank-k pivoted Cholesky of K(X, X): returns (L [rank, n] float64, the factor
+    stored transposed, and the pivots [rank] int32) as device tensors."""
+    n, d = X.shape
+    th, thp = _theta(theta)
+    L = torch.zeros((max(k, 1), max(n, 1)), device=X.device, dtype=torch.float64)
+    piv = torch.zeros(max(k, 1), device=X.device, dtype=torch.int32)
+    rank = C.c_int(0)
+    x, _ = _dptr(X, "X")
+    ctx.check(N.lib().gp_pivoted_cholesky(ctx.handle, x, n, d, thp, k, L.data_ptr(), max(n, 1),
+                                          piv.data_ptr(), C.byref(rank)))
+    return L[:rank.value], piv[:rank.value]
 
 
 def gp_prior_sample(ctx: Context, Xq, theta, t, W, out=None):

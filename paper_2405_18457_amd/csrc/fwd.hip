@@ -392,16 +392,25 @@ __device__ __forceinline__ void tile_a_xt(float bx, float ni, float ajl, float a
   }
 }
 
+// One column step of the cross-term pipeline.  bh/bl hold the V tiles of step k;
+// the tiles of step k+1 are loaded into nbh/nbl at the start of the step, so their
+// latency is covered by a whole step of work.
 template <int MODE, int CT, int RS>
 __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS], const float (&ni)[RS],
                                              float ajl, float ajh, float& njl, float& njh,
-                                             bf16x8 (&bh)[CT], bf16x8 (&bl)[CT],
+                                             const bf16x8 (&bh)[CT], const bf16x8 (&bl)[CT],
+                                             bf16x8 (&nbh)[CT], bf16x8 (&nbl)[CT],
                                              const bf16x8& a0h, const bf16x8& a0l, bf16x8& n0h,
                                              bf16x8& n0l, f32x4 (&acc)[RS][CT],
                                              const float* __restrict__ xnext, float mult,
                                              const uint16_t* __restrict__ vh_next,
                                              const uint16_t* __restrict__ vl_next) {
   constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    nbh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
+    if (MODE == P_BF16X3) nbl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
+  }
   const float rl = xnext[0];
   const float rh = xnext[16 * 4];
   bf16x8 ah = a0h, al = a0l;
@@ -410,6 +419,8 @@ __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS], const float 
     bf16x8 nh, nl;
     tile_a_xt<MODE>(bx[r + 1], ni[r + 1], ajl, ajh, nh, nl);
     mfma_tiles<MODE, CT>(acc[r], ah, al, bh, bl);
+    if (r == 0)
+      __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, (MODE == P_BF16X3 ? 2 : 1) * CT + 2, 0);
     interleave<NM + 2, 4>();
     __builtin_amdgcn_sched_barrier(0);
     ah = nh;
@@ -418,24 +429,7 @@ __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS], const float 
   njl = rl * mult;
   njh = rh * mult;
   tile_a_xt<MODE>(bx[0], ni[0], njl, njh, n0h, n0l);
-  if (MODE == P_BF16X3) {
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-      acc[RS - 1][ct] =
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[RS - 1][ct], 0, 0, 0);
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      acc[RS - 1][ct] =
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[RS - 1][ct], 0, 0, 0);
-      bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
-    }
-  }
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    acc[RS - 1][ct] =
-        __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[RS - 1][ct], 0, 0, 0);
-    bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
-  }
+  mfma_tiles<MODE, CT>(acc[RS - 1], ah, al, bh, bl);
   interleave<NM + 2, 4>();
   __builtin_amdgcn_sched_barrier(0);
 }
@@ -478,23 +472,23 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
     const int64_t voff = l16 * 32 + 8 * g;
     const int64_t tstride = (int64_t)CT * 512;
     float J0l, J0h, J1l, J1h;
-    bf16x8 bh[CT], bl[CT];
+    bf16x8 B0h[CT], B0l[CT], B1h[CT], B1l[CT];
     bf16x8 A0h, A0l, A1h, A1l;
     J0l = xb[s0 * kJStep * 4] * mult;
     J0h = xb[(s0 * kJStep + 16) * 4] * mult;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      bh[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
+      B0h[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
       if (MODE == P_BF16X3)
-        bl[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
+        B0l[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
     }
     tile_a_xt<MODE>(bx[0], ni[0], J0l, J0h, A0h, A0l);
     int64_t st = s0;
     int left = kChunk;
     while (true) {
       int64_t nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step_xt<MODE, CT, RS>(bx, ni, J0l, J0h, J1l, J1h, bh, bl, A0h, A0l, A1h, A1l, acc,
-                                 xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
+      bf16_step_xt<MODE, CT, RS>(bx, ni, J0l, J0h, J1l, J1h, B0h, B0l, B1h, B1l, A0h, A0l, A1h,
+                                 A1l, acc, xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
                                  vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
@@ -502,8 +496,8 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
         left = kChunk;
       }
       nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step_xt<MODE, CT, RS>(bx, ni, J1l, J1h, J0l, J0h, bh, bl, A1h, A1l, A0h, A0l, acc,
-                                 xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
+      bf16_step_xt<MODE, CT, RS>(bx, ni, J1l, J1h, J0l, J0h, B1h, B1l, B0h, B0l, A1h, A1l, A0h,
+                                 A0l, acc, xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
                                  vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {

@@ -209,6 +209,34 @@ hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* statu
 
 // ---------------------------------------------------------------- AP / SGD (solve.hip)
 constexpr int kMaxAPBlock = 2016;  // padded AP block size limit (multiple of 32)
+
+// ---------------------------------------------------------------- preconditioner
+// Pivoted-Cholesky construction state (device memory): current pivot, its
+// remaining diagonal, the rank reached and a stop flag (rank deficiency).
+struct PcState {
+  int64_t p;
+  int stop;
+  int rank;
+  double dp;
+};
+constexpr int kMaxPrecondRank = 2016;  // padded rank limit (explicit inverse in LDS)
+int pc_parts(int64_t n);
+hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
+// One pivoted-Cholesky step j of k (column j for the current pivot, then the next pivot).
+hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a2, double* L,
+                   int64_t ldl, int j, int k, double* diag, PcState* s, double* lp, double* pval,
+                   int64_t* pidx, int32_t* piv, hipStream_t st);
+// A (kp x kp) = sigma^2 I + L^T L on the leading k x k block, identity elsewhere.
+hipError_t pc_gram(const double* L, int64_t ldl, int k, int64_t n, double* part,
+                   int64_t part_cap, double* A, int kp, double s2, hipStream_t st);
+int64_t pc_gram_parts(int64_t n, int k);
+// M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank).
+hipError_t pc_inverse(const double* C, int kp, double* M, hipStream_t st);
+int64_t pc_apply_parts(int64_t n, int k, int c);
+// Z = (R - L M L^T R) / sigma^2 for c columns (T, S: k x c scratch).
+hipError_t pc_apply(const double* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
+                    const float* R, int64_t ldr, int c, double* part, double* T, double* S,
+                    float* Z, int64_t ldz, double s2, hipStream_t st);
 // FP64 H[I, I] for every contiguous block of b rows, lower triangle, padded to P x P.
 hipError_t ap_build_blocks(const float* xp, int DP, int d, int64_t n, int b, int P, double a2,
                            double s2, double* M, hipStream_t st);

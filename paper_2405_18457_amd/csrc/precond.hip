@@ -1,0 +1,402 @@
+// Rank-k pivoted Cholesky preconditioner of conjugate gradients (App. B: CG
+// with its preconditioner P(.), a rank-100 pivoted Cholesky factor in the
+// paper's experiments).
+//
+//   construction   greedy partial Cholesky of K, one pivot per step: the row
+//                  with the largest remaining diagonal (lowest index on ties),
+//                  l_j = (K[:, p] - L[:, :j] L[p, :j]^T) / sqrt(d_p),
+//                  d <- d - l_j^2.  Two launches per step (column + pivot);
+//                  the pivot stays in device memory, so the k steps run without
+//                  host round trips.  Kernel columns are evaluated in FP64 from
+//                  the raw inputs.
+//   inverse        M = (sigma^2 I + L^T L)^-1 (k x k, FP64): the Gram matrix on
+//                  FP64 MFMA, a tiled Cholesky (kchol) and k/4 triangular solves
+//                  against identity columns.
+//   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), both skinny
+//                  products on FP64 MFMA with FP64 accumulation; the subtraction
+//                  cancels most of R, which is why nothing here is below FP64.
+//
+// L is stored transposed, L[t * ldl + i] (row t = factor column t), so that both
+// the construction's per-row dot products and the MFMA operand loads are
+// coalesced along i.
+#include "gpk.h"
+
+namespace gpk {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPcThreads = 256;
+
+__global__ void kpc_init(double* __restrict__ diag, int64_t n, double a2, PcState* __restrict__ s,
+                         int32_t* __restrict__ piv) {
+  const int64_t i = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  if (i < n) diag[i] = a2;
+  if (i == 0) {
+    s->p = 0;  // every diagonal entry equals a^2: the tie goes to index 0
+    s->stop = 0;
+    s->rank = 0;
+    s->dp = a2;
+    piv[0] = 0;
+  }
+}
+
+// (value, index) maximum with the lowest index on ties; idx < 0 marks "none".
+__device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t bi) {
+  if (i < 0) return false;
+  if (bi < 0) return true;
+  return v > bv || (v == bv && i < bi);
+}
+
+__device__ void block_argmax(double v, int64_t i, double* sv, int64_t* si, double* out_v,
+                             int64_t* out_i) {
+  const int tid = threadIdx.x;
+  sv[tid] = v;
+  si[tid] = i;
+  __syncthreads();
+  for (int off = kPcThreads / 2; off > 0; off >>= 1) {
+    if (tid < off && better(sv[tid + off], si[tid + off], sv[tid], si[tid])) {
+      sv[tid] = sv[tid + off];
+      si[tid] = si[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *out_v = sv[0];
+    *out_i = si[0];
+  }
+}
+
+// Step j: factor column j for pivot s->p, diagonal update, per-block argmax.
+__global__ __launch_bounds__(kPcThreads) void kpc_column(
+    const float* __restrict__ X, int64_t n, int d, const double* __restrict__ ell, double a2,
+    double* __restrict__ L, int64_t ldl, int j, double* __restrict__ diag,
+    const PcState* __restrict__ s, const double* __restrict__ lp, double* __restrict__ pval,
+    int64_t* __restrict__ pidx) {
+  __shared__ double sv[kPcThreads];
+  __shared__ int64_t si[kPcThreads];
+  const int64_t i = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  const int64_t p = s->p;
+  const double dp = s->dp;
+  const bool stop = s->stop != 0;
+  double nd = 0.0;
+  int64_t ni = -1;
+  if (!stop && i < n) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double t = (double)X[i * d + k] / ell[k] - (double)X[p * d + k] / ell[k];
+      r2 += t * t;
+    }
+    const double r = sqrt(3.0 * r2);
+    double kv = a2 * (1.0 + r) * exp(-r);
+    for (int t = 0; t < j; ++t) kv -= L[(int64_t)t * ldl + i] * lp[t];
+    const double l = kv / sqrt(dp);
+    L[(int64_t)j * ldl + i] = l;
+    double di = diag[i] - l * l;
+    if (i == p) di = 0.0;
+    diag[i] = di;
+    nd = di;
+    ni = i;
+  }
+  block_argmax(nd, ni, sv, si, pval + blockIdx.x, pidx + blockIdx.x);
+}
+
+// After step j: the next pivot from the block maxima, its remaining diagonal and
+// its factor row L[p, :j+1] (gathered for the next step's dot products).
+__global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict__ pval,
+                                                        const int64_t* __restrict__ pidx,
+                                                        int nparts, const double* __restrict__ L,
+                                                        int64_t ldl, int j, int k,
+                                                        PcState* __restrict__ s,
+                                                        double* __restrict__ lp,
+                                                        int32_t* __restrict__ piv) {
+  __shared__ double sv[kPcThreads];
+  __shared__ int64_t si[kPcThreads];
+  __shared__ double bv;
+  __shared__ int64_t bi;
+  const bool stop = s->stop != 0;
+  __syncthreads();
+  if (stop) return;  // uniform across the block
+  double v = 0.0;
+  int64_t idx = -1;
+  for (int b = threadIdx.x; b < nparts; b += kPcThreads)
+    if (better(pval[b], pidx[b], v, idx)) {
+      v = pval[b];
+      idx = pidx[b];
+    }
+  block_argmax(v, idx, sv, si, &bv, &bi);
+  __syncthreads();
+  if (j + 1 >= k) {
+    if (threadIdx.x == 0) s->rank = j + 1;
+    return;
+  }
+  if (bi >= 0 && bv > 0.0) {
+    for (int t = threadIdx.x; t <= j; t += kPcThreads) lp[t] = L[(int64_t)t * ldl + bi];
+    if (threadIdx.x == 0) {
+      s->rank = j + 1;
+      s->p = bi;
+      s->dp = bv;
+      piv[j + 1] = (int32_t)bi;
+    }
+  } else if (threadIdx.x == 0) {
+    s->rank = j + 1;
+    s->stop = 1;
+  }
+}
+
+// part[z][a][b] = sum over rows i of chunk z of L[a][i] * Bop(i, b), a < ka, b < nb,
+// with Bop(i, b) = B[i * brs + b * bcs].  One wave: 16 factor rows a x 16*NBT
+// columns b, v_mfma_f64_16x16x4f64 over 4 rows i per instruction
+// (A lane: L[a0 + l%16][i + l/16]; B lane: Bop(i + l/16, b0 + l%16);
+//  D lane q: (a0 + 4q + l/16, b0 + l%16)).
+template <int NBT, typename TB>
+__global__ __launch_bounds__(256) void kpc_tn(const double* __restrict__ L, int64_t ldl, int ka,
+                                              int64_t n, const TB* __restrict__ B, int64_t brs,
+                                              int64_t bcs, int nb, int64_t csize,
+                                              double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int a0 = (blockIdx.x * 4 + wave) * 16;
+  const int b0 = blockIdx.y * 16 * NBT;
+  const int64_t i0 = (int64_t)blockIdx.z * csize;
+  const int64_t i1 = i0 + csize < n ? i0 + csize : n;
+  const int la = lane & 15, lk = lane >> 4;
+  f64x4 acc[NBT];
+#pragma unroll
+  for (int t = 0; t < NBT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int a = a0 + la;
+  for (int64_t i = i0; i < i1; i += 4) {
+    const int64_t ii = i + lk;
+    const bool rok = ii < i1;
+    const double av = (a < ka && rok) ? L[(int64_t)a * ldl + ii] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NBT; ++t) {
+      const int b = b0 + 16 * t + la;
+      const double bv = (b < nb && rok) ? (double)B[ii * brs + (int64_t)b * bcs] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+    }
+  }
+  if (a0 >= ka) return;
+#pragma unroll
+  for (int t = 0; t < NBT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ar = a0 + 4 * q + lk;
+      const int bc = b0 + 16 * t + la;
+      if (ar < ka && bc < nb) part[((int64_t)blockIdx.z * ka + ar) * nb + bc] = acc[t][q];
+    }
+}
+
+// out[a][b] = sum_z part[z][a][b] (fixed order).  With diag_add: out is the
+// kp x kp Cholesky input sigma^2 I + G, identity on the padding.
+__global__ void kpc_sum(const double* __restrict__ part, int nz, int ka, int nb,
+                        double* __restrict__ out, int ldo, int kp, double diag_add, int square) {
+  const int64_t t = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  if (square) {
+    if (t >= (int64_t)kp * kp) return;
+    const int a = (int)(t / kp), b = (int)(t % kp);
+    double v;
+    if (a < ka && b < ka) {
+      v = 0.0;
+      for (int z = 0; z < nz; ++z) v += part[((int64_t)z * ka + a) * nb + b];
+      if (a == b) v += diag_add;
+    } else {
+      v = a == b ? 1.0 : 0.0;
+    }
+    out[(int64_t)a * ldo + b] = v;
+  } else {
+    if (t >= (int64_t)ka * nb) return;
+    const int a = (int)(t / nb), b = (int)(t % nb);
+    double v = 0.0;
+    for (int z = 0; z < nz; ++z) v += part[((int64_t)z * ka + a) * nb + b];
+    out[(int64_t)a * ldo + b] = v;
+  }
+}
+
+// Columns c0..c0+3 of M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp):
+// forward and backward substitution against identity columns.
+__global__ __launch_bounds__(256) void kpc_inverse(const double* __restrict__ C, int kp,
+                                                   double* __restrict__ M) {
+  constexpr int CW = 4;
+  __shared__ double y[kMaxPrecondRank][CW];
+  __shared__ double red[4][CW];
+  const int c0 = blockIdx.x * CW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < kp * CW; e += 256) {
+    const int i = e / CW, q = e % CW;
+    y[i][q] = (i == c0 + q) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < kp; ++k) {
+    double acc[CW] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = tid; j < k; j += 256) {
+      const double l = C[(int64_t)k * kp + j];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) acc[q] += l * y[j][q];
+    }
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      double v = acc[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (tid < CW) {
+      const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      y[k][tid] = (y[k][tid] - s) / C[(int64_t)k * kp + k];
+    }
+    __syncthreads();
+  }
+  for (int k = kp - 1; k >= 0; --k) {
+    if (tid < CW) y[k][tid] /= C[(int64_t)k * kp + k];
+    __syncthreads();
+    for (int j = tid; j < k; j += 256) {
+      const double l = C[(int64_t)k * kp + j];
+#pragma unroll
+      for (int q = 0; q < CW; ++q) y[j][q] -= l * y[k][q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kp * CW; e += 256) {
+    const int i = e / CW, q = e % CW;
+    if (c0 + q < kp) M[(int64_t)i * kp + c0 + q] = y[i][q];
+  }
+}
+
+// S[a][b] = sum_t M[a][t] T[t][b], a < k, b < nb (M has leading dimension kp).
+__global__ void kpc_small(const double* __restrict__ M, int kp, const double* __restrict__ T,
+                          int k, int nb, double* __restrict__ S) {
+  const int64_t e = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  if (e >= (int64_t)k * nb) return;
+  const int a = (int)(e / nb), b = (int)(e % nb);
+  double v = 0.0;
+  for (int t = 0; t < k; ++t) v += M[(int64_t)a * kp + t] * T[(int64_t)t * nb + b];
+  S[e] = v;
+}
+
+// Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2.  One wave: 16 rows i x
+// 16*NBT columns, FP64 MFMA over 4 factor columns t per instruction
+// (A lane: L[t + l/16][i0 + l%16]; B lane: S[t + l/16][c0 + l%16]).
+template <int NBT>
+__global__ __launch_bounds__(256) void kpc_apply(const double* __restrict__ L, int64_t ldl, int k,
+                                                 int64_t n, const double* __restrict__ S, int nb,
+                                                 const float* __restrict__ R, int64_t ldr,
+                                                 float* __restrict__ Z, int64_t ldz, double s2) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int c0 = blockIdx.y * 16 * NBT;
+  const int la = lane & 15, lk = lane >> 4;
+  f64x4 acc[NBT];
+#pragma unroll
+  for (int t = 0; t < NBT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t ia = i0 + la;
+  for (int t0 = 0; t0 < k; t0 += 4) {
+    const int t = t0 + lk;
+    const double av = (t < k && ia < n) ? L[(int64_t)t * ldl + ia] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NBT; ++u) {
+      const int c = c0 + 16 * u + la;
+      const double bv = (t < k && c < nb) ? S[(int64_t)t * nb + c] : 0.0;
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+    }
+  }
+  const double inv = 1.0 / s2;
+#pragma unroll
+  for (int u = 0; u < NBT; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + 4 * q + lk;
+      const int c = c0 + 16 * u + la;
+      if (i < n && c < nb) Z[i * ldz + c] = (float)(((double)R[i * ldr + c] - acc[u][q]) * inv);
+    }
+}
+
+int blocks_of(int64_t count) { return (int)((count + kPcThreads - 1) / kPcThreads); }
+
+}  // namespace
+
+int pc_parts(int64_t n) { return blocks_of(n); }
+
+hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st) {
+  hipLaunchKernelGGL(kpc_init, dim3(blocks_of(n > 0 ? n : 1)), dim3(kPcThreads), 0, st, diag, n,
+                     a2, s, piv);
+  return hipGetLastError();
+}
+
+hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a2, double* L,
+                   int64_t ldl, int j, int k, double* diag, PcState* s, double* lp, double* pval,
+                   int64_t* pidx, int32_t* piv, hipStream_t st) {
+  const int nparts = blocks_of(n);
+  hipLaunchKernelGGL(kpc_column, dim3(nparts), dim3(kPcThreads), 0, st, X, n, d, ell, a2, L, ldl,
+                     j, diag, s, lp, pval, pidx);
+  hipLaunchKernelGGL(kpc_pivot, dim3(1), dim3(kPcThreads), 0, st, pval, pidx, nparts, L, ldl, j,
+                     k, s, lp, piv);
+  return hipGetLastError();
+}
+
+// Row-chunk length so that the split products launch about `target` workgroups.
+static int64_t chunk_rows(int64_t n, int64_t tiles, int64_t target) {
+  int64_t nz = target / (tiles > 0 ? tiles : 1);
+  if (nz < 1) nz = 1;
+  int64_t cs = (n + nz - 1) / nz;
+  cs = (cs + 15) / 16 * 16;
+  return cs < 64 ? 64 : cs;
+}
+
+hipError_t pc_gram(const double* L, int64_t ldl, int k, int64_t n, double* part,
+                   int64_t part_cap, double* A, int kp, double s2, hipStream_t st) {
+  const int64_t xt = (k + 63) / 64, yt = (k + 63) / 64;
+  int64_t cs = chunk_rows(n, xt * yt, 2048);
+  int64_t nz = (n + cs - 1) / cs;
+  while (nz * k * k > part_cap) {
+    cs *= 2;
+    nz = (n + cs - 1) / cs;
+  }
+  if (k > 0 && n > 0)
+    hipLaunchKernelGGL((kpc_tn<4, double>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, L,
+                       (int64_t)1, ldl, k, cs, part);
+  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
+                     (int)((k > 0 && n > 0) ? nz : 0), k, k, A, kp, kp, s2, 1);
+  return hipGetLastError();
+}
+
+int64_t pc_gram_parts(int64_t n, int k) {
+  const int64_t xt = (k + 63) / 64;
+  const int64_t cs = chunk_rows(n, xt * xt, 2048);
+  return ((n + cs - 1) / cs) * (int64_t)k * k;
+}
+
+hipError_t pc_inverse(const double* C, int kp, double* M, hipStream_t st) {
+  if (kp > kMaxPrecondRank) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kpc_inverse, dim3((kp + 3) / 4), dim3(256), 0, st, C, kp, M);
+  return hipGetLastError();
+}
+
+int64_t pc_apply_parts(int64_t n, int k, int c) {
+  const int64_t cs = chunk_rows(n, (k + 63) / 64 * ((c + 79) / 80), 2048);
+  return ((n + cs - 1) / cs) * (int64_t)k * c;
+}
+
+hipError_t pc_apply(const double* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
+                    const float* R, int64_t ldr, int c, double* part, double* T, double* S,
+                    float* Z, int64_t ldz, double s2, hipStream_t st) {
+  if (k > 0 && n > 0) {
+    const int64_t xt = (k + 63) / 64, yt = (c + 79) / 80;
+    const int64_t cs = chunk_rows(n, xt * yt, 2048);
+    const int64_t nz = (n + cs - 1) / cs;
+    hipLaunchKernelGGL((kpc_tn<5, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R,
+                       ldr, (int64_t)1, c, cs, part);
+    hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
+                       (int)nz, k, c, T, c, 0, 0.0, 0);
+    hipLaunchKernelGGL(kpc_small, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, M, kp,
+                       T, k, c, S);
+  }
+  if (n > 0)
+    hipLaunchKernelGGL((kpc_apply<5>), dim3((n + 63) / 64, (c + 79) / 80), dim3(256), 0, st, L,
+                       ldl, k, n, S, c, R, ldr, Z, ldz, s2);
+  return hipGetLastError();
+}
+
+}  // namespace gpk

@@ -25,12 +25,13 @@ namespace {
 enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
-  B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_COUNT
+  B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
 constexpr int64_t kSafetyCap = 100000;
-constexpr int kProfClasses = 5;
+constexpr int kProfClasses = 6;
 
 struct Packed {
   float* xp = nullptr;
@@ -183,6 +184,15 @@ int check_mat(gp_ctx* ctx, const char* name, const void* p, int64_t rows, int64_
   return GP_OK;
 }
 
+int check_precond(gp_ctx* ctx, const gp_solver_cfg& cfg) {
+  if (cfg.precond_rank < 0 || cfg.precond_rank > kMaxPrecondRank)
+    return fail(ctx, GP_ERR_INVALID_ARG, "precond_rank %d outside [0, %d]", cfg.precond_rank,
+                kMaxPrecondRank);
+  if (cfg.precond_rank > 0 && cfg.solver != GP_CG)
+    return fail(ctx, GP_ERR_INVALID_ARG, "the pivoted-Cholesky preconditioner is for CG only");
+  return GP_OK;
+}
+
 int check_prec(gp_ctx* ctx, int prec) {
   if (prec != GP_FP32 && prec != GP_BF16X3 && prec != GP_BF16)
     return fail(ctx, GP_ERR_INVALID_ARG, "unknown precision %d", prec);
@@ -307,7 +317,7 @@ int col_sums(gp_ctx* ctx, const float* A, const float* B, int64_t n, int64_t lda
 struct SolveState {
   int64_t n;
   int c;
-  float *Bt, *Ut, *R, *Dv, *HD;
+  float *Bt, *Ut, *R, *Dv, *HD, *Z = nullptr;
   double *scale_d, *gamma, *alpha, *beta, *rnorm;
   float* scale_f;
   int* status;
@@ -391,14 +401,117 @@ int solve_setup(gp_ctx* ctx, const float* B, int64_t ldb, const float* U, int64_
   return GP_OK;
 }
 
-// R = Bt - H Ut with the given precision; optionally D = R; gamma = R.R.
+// ------------------------------------------------------------ preconditioner
+// Rank-k pivoted-Cholesky preconditioner of CG (App. B): P = L L^T + sigma^2 I,
+// applied as P^-1 through the Woodbury identity with M = (sigma^2 I + L^T L)^-1.
+struct Precond {
+  int k = 0;         // rank reached (0: P = sigma^2 I is not used, see `active`)
+  int kp = 0;        // k rounded up to 32 (Cholesky / inverse tile)
+  int64_t ldl = 0;   // leading dimension of the transposed factor L[t * ldl + i]
+  int64_t n = 0;
+  double* L = nullptr;
+  double* M = nullptr;
+  double s2 = 0.0;
+  bool active = false;
+};
+
+// Greedy construction into L [k, ldl] / piv [k]; returns the rank reached.
+int pc_construct(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, int k,
+                 double* L, int64_t ldl, int32_t* piv, int* rank) {
+  *rank = 0;
+  if (k <= 0 || n <= 0) return GP_OK;
+  double *diag, *lp, *pval, *ell;
+  int64_t* pidx;
+  PcState* st;
+  CHK(ensure(ctx, B_PCDIAG, (size_t)n, &diag));
+  CHK(ensure(ctx, B_PCLP, (size_t)k, &lp));
+  CHK(ensure(ctx, B_PCPV, (size_t)pc_parts(n), &pval));
+  CHK(ensure(ctx, B_PCPI, (size_t)pc_parts(n), &pidx));
+  CHK(ensure(ctx, B_PCST, 1, &st));
+  CHK(ensure(ctx, B_PCELL, (size_t)d, &ell));
+  CHK(ensure_pinned(ctx, (size_t)std::max(d, 2)));
+  std::memcpy(ctx->hpin, theta, (size_t)d * sizeof(double));
+  HIPCHK(hipMemcpyAsync(ell, ctx->hpin, (size_t)d * sizeof(double), hipMemcpyHostToDevice,
+                        ctx->stream));
+  const double a2 = theta[d] * theta[d];
+  HIPCHK(pc_init(diag, n, a2, st, piv, ctx->stream));
+  for (int j = 0; j < k; ++j)
+    HIPCHK(pc_step(X, n, d, ell, a2, L, ldl, j, k, diag, st, lp, pval, pidx, piv, ctx->stream));
+  PcState hs;
+  HIPCHK(hipMemcpyAsync(ctx->hpin, st, sizeof(PcState), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(&hs, ctx->hpin, sizeof hs);
+  *rank = hs.rank;
+  return GP_OK;
+}
+
+int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, int k_req,
+             Precond& pc) {
+  pc = Precond{};
+  pc.n = n;
+  pc.s2 = theta[d + 1] * theta[d + 1];
+  pc.active = true;
+  const int k = (int)std::min<int64_t>(k_req, n);
+  if (k <= 0) return GP_OK;
+  pc.ldl = round_up(n, 64);
+  int32_t* piv;
+  CHK(ensure(ctx, B_PCL, (size_t)k * pc.ldl, &pc.L));
+  CHK(ensure(ctx, B_PCPIV, (size_t)k, &piv));
+  CHK(pc_construct(ctx, X, n, d, theta, k, pc.L, pc.ldl, piv, &pc.k));
+  if (pc.k == 0) return GP_OK;
+  pc.kp = (int)round_up(pc.k, 32);
+  double *part, *A;
+  int* stat;
+  const int64_t pcap = pc_gram_parts(n, pc.k);
+  CHK(ensure(ctx, B_PCPART, (size_t)pcap, &part));
+  CHK(ensure(ctx, B_PCA, (size_t)pc.kp * pc.kp, &A));
+  CHK(ensure(ctx, B_PCM, (size_t)pc.kp * pc.kp, &pc.M));
+  CHK(ensure(ctx, B_PCSTAT, 1, &stat));
+  HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
+  HIPCHK(pc_gram(pc.L, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
+  HIPCHK(ap_cholesky(A, 1, pc.kp, stat, ctx->stream));
+  HIPCHK(pc_inverse(A, pc.kp, pc.M, ctx->stream));
+  int hst = 0;
+  HIPCHK(hipMemcpyAsync(ctx->hpin, stat, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(&hst, ctx->hpin, sizeof(int));
+  if (hst) return fail(ctx, GP_ERR_BREAKDOWN, "preconditioner: sigma^2 I + L^T L not positive definite");
+  return GP_OK;
+}
+
+// Z = P^-1 R for the c columns of R (ld ldr).
+int pc_apply_cols(gp_ctx* ctx, const Precond& pc, const float* R, int64_t ldr, int c, float* Z,
+                  int64_t ldz) {
+  double *part = nullptr, *T = nullptr, *S = nullptr;
+  if (pc.k > 0) {
+    CHK(ensure(ctx, B_PCPART, (size_t)std::max(pc_apply_parts(pc.n, pc.k, c),
+                                               pc_gram_parts(pc.n, pc.k)), &part));
+    CHK(ensure(ctx, B_PCT, (size_t)pc.k * c, &T));
+    CHK(ensure(ctx, B_PCS, (size_t)pc.k * c, &S));
+  }
+  ProfScope ps(ctx, 5);
+  HIPCHK(pc_apply(pc.L, pc.ldl, pc.k, pc.n, pc.M, pc.kp, R, ldr, c, part, T, S, Z, ldz, pc.s2,
+                  ctx->stream));
+  return GP_OK;
+}
+
+// R = Bt - H Ut with the given precision; optionally D = R (or P^-1 R);
+// gamma = R.R (or R.P^-1 R); rnorm = ||R||.
 int true_residual(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
-                  int prec, bool set_d) {
+                  int prec, bool set_d, const Precond* pc = nullptr) {
   CHK(kprod(ctx, px, px, s.Ut, s.c, s.c, s.HD, s.c, prec, a2_of(theta, d), s.Ut, s.c,
             s2_of(theta, d)));
-  HIPCHK(residual_init(s.Bt, s.HD, s.R, s.Dv, s.n, s.c, s.c, s.partial, s.nb, set_d,
+  const bool use_pc = pc && pc->active;
+  HIPCHK(residual_init(s.Bt, s.HD, s.R, s.Dv, s.n, s.c, s.c, s.partial, s.nb, set_d && !use_pc,
                        ctx->stream));
-  HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, s.gamma, s.rnorm, s.status, ctx->stream));
+  HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, use_pc ? nullptr : s.gamma, s.rnorm, s.status,
+                            ctx->stream));
+  if (use_pc) {
+    CHK(pc_apply_cols(ctx, *pc, s.R, s.c, s.c, s.Z, s.c));
+    HIPCHK(col_dot_partial(s.R, s.Z, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+    HIPCHK(col_reduce(s.partial, s.nb, s.c, s.gamma, ctx->stream));
+    if (set_d) HIPCHK(copy_cols(s.Z, s.c, s.n, s.c, s.Dv, s.c, ctx->stream));
+  }
   return GP_OK;
 }
 
@@ -407,16 +520,27 @@ int solve_finish(gp_ctx* ctx, SolveState& s, float* U, int64_t ldu) {
   return GP_OK;
 }
 
-int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
-             const gp_solver_cfg& cfg, gp_solve_stats& stats) {
+int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
+             SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
   const int prec = cfg.precision;
+  Precond pcs;
+  const Precond* pc = nullptr;
+  if (cfg.precond_rank > 0) {
+    {
+      ProfScope ps(ctx, 5);
+      CHK(pc_build(ctx, X, s.n, d, theta, cfg.precond_rank, pcs));
+    }
+    CHK(ensure(ctx, B_Z, (size_t)s.n * s.c, &s.Z));
+    pc = &pcs;
+    stats.precond_rank = pcs.k;
+  }
   const bool mixed = prec != GP_FP32;
   const int64_t cap = cfg.max_epochs > 0 ? (int64_t)std::ceil(cfg.max_epochs - 1e-9) : kSafetyCap;
   const int check = cfg.check_every > 0 ? cfg.check_every : 1;
   const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
 
   // Initial residual r = b~ - H u~ (FP32: it is the true residual).
-  CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true));
+  CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true, pc));
   stats.matvecs += 1;
   int64_t t = 0, since_true = 0;
   double ry = 0, rz = 0;
@@ -437,7 +561,7 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
         // as the inner solver.  Stop when a restart no longer halves the true
         // residual -- the attainable accuracy of the reduced-precision
         // operator has been reached (reported as not converged).
-        CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true));
+        CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true, pc));
         stats.matvecs += 1;
         stats.refinements += 1;
         since_true = 0;
@@ -466,7 +590,7 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
         break;
       }
     }
-    // One CG iteration (Algorithm 1 with P = I), columns in parallel.
+    // One CG iteration (Algorithm 1), columns in parallel.
     CHK(kprod(ctx, px, px, s.Dv, s.c, s.c, s.HD, s.c, prec, a2, s.Dv, s.c, s2));
     stats.matvecs += 1;
     {
@@ -475,13 +599,24 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveSta
       HIPCHK(cg_alpha(s.partial, s.nb, s.c, s.gamma, s.alpha, s.status, ctx->stream));
       HIPCHK(cg_update_ur(s.Ut, s.R, s.Dv, s.HD, s.alpha, s.n, s.c, s.c, s.partial, s.nb,
                           ctx->stream));
-      HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, s.rnorm, s.status, ctx->stream));
-      HIPCHK(cg_update_d(s.Dv, s.R, s.beta, s.n, s.c, s.c, ctx->stream));
+      if (!pc) {
+        HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, s.rnorm, s.status, ctx->stream));
+        HIPCHK(cg_update_d(s.Dv, s.R, s.beta, s.n, s.c, s.c, ctx->stream));
+      }
+    }
+    if (pc) {
+      // p = P(r); beta = r.p / gamma; gamma = r.p; d = p + beta d
+      HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, nullptr, s.rnorm, s.status, ctx->stream));
+      CHK(pc_apply_cols(ctx, *pc, s.R, s.c, s.c, s.Z, s.c));
+      ProfScope ps(ctx, 3);
+      HIPCHK(col_dot_partial(s.R, s.Z, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+      HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, nullptr, s.status, ctx->stream));
+      HIPCHK(cg_update_d(s.Dv, s.Z, s.beta, s.n, s.c, s.c, ctx->stream));
     }
     ++t;
     ++since_true;
     if (mixed && cfg.refine_every > 0 && since_true >= cfg.refine_every) {
-      CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
+      CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false, pc));
       stats.matvecs += 1;
       stats.refinements += 1;
       since_true = 0;
@@ -885,6 +1020,7 @@ void gp_solver_cfg_default(gp_solver_cfg* cfg) {
   cfg->sgd_batches = nullptr;
   cfg->sgd_batches_count = 0;
   cfg->sgd_seed = 0;
+  cfg->precond_rank = 0;
 }
 
 int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, const float* B,
@@ -904,6 +1040,7 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   CHK(check_mat(ctx, "B", B, n, ldb, c));
   CHK(check_mat(ctx, "U", U, n, ldu, c));
   if (!(cfg->tol >= 0.0)) return fail(ctx, GP_ERR_INVALID_ARG, "tol must be >= 0");
+  CHK(check_precond(ctx, *cfg));
   HIPCHK(hipSetDevice(ctx->device));
   if (n == 0 || c == 0) {
     s.converged = 1;
@@ -914,6 +1051,26 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   const int r = solve_dispatch(ctx, px, X, theta, d, B, ldb, U, ldu, c, *cfg, s);
   s.status = r;
   return r;
+}
+
+int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
+                        int k, double* L, int64_t ldl, int32_t* piv, int* rank) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!rank) return fail(ctx, GP_ERR_INVALID_ARG, "rank is NULL");
+  *rank = 0;
+  CHK(check_dims(ctx, d, 1));
+  CHK(check_theta(ctx, theta, d));
+  if (k < 0 || k > kMaxPrecondRank)
+    return fail(ctx, GP_ERR_INVALID_ARG, "k %d outside [0, %d]", k, kMaxPrecondRank);
+  if (n < 0) return fail(ctx, GP_ERR_INVALID_ARG, "n < 0");
+  if (k == 0 || n == 0) return GP_OK;
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  if (!L || !piv) return fail(ctx, GP_ERR_INVALID_ARG, "L or piv is NULL");
+  if (ldl < n) return fail(ctx, GP_ERR_INVALID_ARG, "ldl %lld < n %lld", (long long)ldl,
+                           (long long)n);
+  HIPCHK(hipSetDevice(ctx->device));
+  return pc_construct(ctx, X, n, d, theta, (int)std::min<int64_t>(k, n), L, ldl, piv, rank);
 }
 
 int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const double* theta,
@@ -1095,7 +1252,7 @@ int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* 
   CHK(solve_setup(ctx, B, ldb, U, ldu, px.n, c, s));
   switch (cfg.solver) {
     case GP_CG:
-      CHK(cg_solve(ctx, px, theta, d, s, cfg, stats));
+      CHK(cg_solve(ctx, px, X, theta, d, s, cfg, stats));
       break;
     case GP_AP:
       CHK(ap_solve(ctx, px, X, theta, d, s, cfg, stats));

@@ -259,7 +259,7 @@ __global__ void kcg_beta(const double* __restrict__ partial, int nb, int c,
   const double old = gamma[col];
   beta[col] = old != 0.0 ? g / old : 0.0;
   gamma[col] = old != 0.0 ? g : 0.0;
-  rnorm[col] = sqrt(g);
+  if (rnorm) rnorm[col] = sqrt(g);
 }
 
 __global__ void kgamma(const double* __restrict__ partial, int nb, int c,

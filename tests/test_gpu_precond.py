@@ -1,0 +1,133 @@
+"""Pivoted-Cholesky preconditioner of CG (App. B: Algorithm 1 with P(.), rank 100
+in the paper) on the GPU against the FP64 oracle: the greedy factor itself
+(pivot sequence and factor columns), and preconditioned CG (step-for-step under
+a budget, to tolerance, with bf16x3 products and inside the gradient step)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_common import announce, dev, host, problem, require_gpu
+from oracle import mll, precond, rff, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    require_gpu()
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    yield ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,d,k,dist", [(700, 3, 40, "uniform"), (513, 8, 64, "normal"),
+                                        (300, 1, 25, "normal"), (20, 3, 50, "uniform")])
+def test_pivoted_cholesky_matches_oracle(gp, n, d, k, dist):
+    from paper_2405_18457_amd import api
+    X, _, theta = problem(n, d, 1, seed=11 * n + d, dist=dist,
+                          ell_scale=(0.2, 0.5) if dist == "uniform" else None)
+    announce("pivchol", n, d, k)
+    L, piv = api.gp_pivoted_cholesky(gp, dev(X), theta, k)
+    Lo, po = precond.pivoted_cholesky(X, theta, k)
+    assert L.shape[0] == len(po) == min(k, n)
+    assert list(host(piv).astype(int)) == po
+    np.testing.assert_allclose(host(L).T, Lo, rtol=0, atol=1e-9)
+
+
+def test_pivoted_cholesky_empty_and_invalid(gp):
+    from paper_2405_18457_amd import api
+    X, _, theta = problem(50, 3, 1, seed=2)
+    L, piv = api.gp_pivoted_cholesky(gp, dev(X), theta, 0)
+    assert L.shape[0] == 0 and piv.shape[0] == 0
+    with pytest.raises(api.GPError):
+        api.gp_pivoted_cholesky(gp, dev(X), theta, 5000)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_pcg_steps_match_oracle_under_a_budget(gp, prec):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(900, 3, 9, seed=31, dist="uniform", sigma=0.05, ell_scale=(0.2, 0.5))
+    op = solvers.DenseOperator(X, theta)
+    P = precond.preconditioner(X, theta, 60)
+    announce("pcg-budget", prec)
+    U = torch.zeros((900, 9), device="cuda")
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U,
+                      api.solver_cfg(tol=1e-8, max_epochs=4, precision=prec, precond_rank=60))
+    assert st["iterations"] == 4 and not st["converged"] and st["precond_rank"] == 60
+    Uo, so = solvers.cg(op, B, tol=1e-8, max_epochs=4, precond=P)
+    np.testing.assert_allclose(host(U), Uo, rtol=2e-3, atol=2e-4 * np.abs(Uo).max())
+    assert st["relres_y"] == pytest.approx(so["relres_y"], rel=2e-3)
+    assert st["relres_z"] == pytest.approx(so["relres_z"], rel=2e-3)
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,d,c,sigma,k", [(2000, 3, 65, 0.05, 100), (1500, 8, 17, 0.2, 50)])
+def test_pcg_reaches_tolerance_in_fewer_iterations(gp, n, d, c, sigma, k, prec):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(n, d, c, seed=n + 7 * c, dist="uniform" if d == 3 else "normal",
+                          sigma=sigma, ell_scale=(0.2, 0.5) if d == 3 else None)
+    op = solvers.DenseOperator(X, theta)
+    announce("pcg-tol", n, d, c, k, prec)
+    U0 = torch.zeros((n, c), device="cuda")
+    s0 = api.gp_solve(gp, dev(X), theta, dev(B), U0, api.solver_cfg(tol=1e-2, precision=prec))
+    U = torch.zeros((n, c), device="cuda")
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U,
+                      api.solver_cfg(tol=1e-2, precision=prec, precond_rank=k))
+    ry, rz = solvers.true_relres(op, B, host(U))
+    assert st["converged"] and ry <= 1.02e-2 and rz <= 1.02e-2, (st, ry, rz)
+    Uo, so = solvers.cg(op, B, tol=1e-2, precond=precond.preconditioner(X, theta, k))
+    print("iterations plain / preconditioned / oracle:", s0["iterations"], st["iterations"],
+          so["iterations"])
+    assert 0.7 * so["iterations"] - 2 <= st["iterations"] <= 1.5 * so["iterations"] + 6, (st, so)
+    assert st["iterations"] < s0["iterations"]
+
+
+def test_precond_rank_validation(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, B, theta = problem(100, 3, 3, seed=5)
+    U = torch.zeros((100, 3), device="cuda")
+    with pytest.raises(api.GPError):
+        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(precond_rank=3000))
+    with pytest.raises(api.GPError):
+        api.gp_solve(gp, dev(X), theta, dev(B), U,
+                     api.solver_cfg(solver=api.GP_AP, precond_rank=10, ap_block=50))
+    # rank above n is capped at n (P = H: one iteration)
+    st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-4, precond_rank=500))
+    assert st["precond_rank"] == 100 and st["converged"] and st["iterations"] <= 2
+
+
+def test_pathwise_gradient_with_preconditioner(gp):
+    """Gradient estimate with preconditioned CG stopped at tau = 1e-2 against the
+    oracle estimator with exact solves and the same random features (workload A
+    shape).  The bound is the one the unpreconditioned solve meets: at tau = 1e-2
+    the solve error itself is of order 1e-3 to 1e-2 in the gradient."""
+    from paper_2405_18457_amd import api
+    import torch
+    w = wl.WORKLOADS["A"]
+    X = wl.draw_inputs(w)
+    tr = wl.truth_draws(w)
+    y = rff.truth_targets_exact(X, tr["ell"], 1.0, w.sigma, tr["w"], tr["noise"]).astype(np.float32)
+    dr = wl.model_pathwise_draws(w)
+    theta = np.concatenate([tr["ell"], [1.0, w.sigma]])
+    U = torch.zeros((w.n, w.s + 1), device="cuda")
+    cfg = api.solver_cfg(tol=1e-2, precision=api.GP_BF16X3, precond_rank=100)
+    announce("grad-tau-precond")
+    g, st = api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_PATHWISE, U, cfg,
+                            rff_t=dev(dr["t"]), rff_W=dev(dr["W"]), w_eps=dev(dr["w_eps"]))
+    B = rff.pathwise_rhs(X, y, theta, dr["t"], dr["W"], dr["w_eps"])
+    ref = mll.pathwise_estimate(X, y, theta, B[:, 1:])
+    err = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    # the same algorithm in FP64: preconditioned CG stopped at the same tau
+    op = solvers.DenseOperator(X, theta)
+    Uo, so = solvers.cg(op, B, tol=1e-2, precond=precond.preconditioner(X, theta, 100))
+    go = mll.pathwise_estimate(X, y, theta, B[:, 1:], solutions=Uo)
+    err_o = float(np.linalg.norm(go - ref) / np.linalg.norm(ref))
+    print("gradient relative error at tau=1e-2, rank-100 preconditioning: gpu", err, "oracle", err_o,
+          st, so["iterations"])
+    assert st["converged"] and st["precond_rank"] == 100
+    assert st["true_relres_y"] <= 1e-2 and st["true_relres_z"] <= 1e-2
+    assert err <= max(2.0 * err_o, 1e-3)
