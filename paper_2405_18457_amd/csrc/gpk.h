@@ -226,15 +226,17 @@ hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv,
 hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a2, double* L,
                    int64_t ldl, int j, int k, double* diag, PcState* s, double* lp, double* pval,
                    int64_t* pidx, int32_t* piv, hipStream_t st);
+// FP32 copy of the factor, used by the products below.
+hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32, hipStream_t st);
 // A (kp x kp) = sigma^2 I + L^T L on the leading k x k block, identity elsewhere.
-hipError_t pc_gram(const double* L, int64_t ldl, int k, int64_t n, double* part,
+hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
                    int64_t part_cap, double* A, int kp, double s2, hipStream_t st);
 int64_t pc_gram_parts(int64_t n, int k);
 // M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank).
 hipError_t pc_inverse(const double* C, int kp, double* M, hipStream_t st);
 int64_t pc_apply_parts(int64_t n, int k, int c);
 // Z = (R - L M L^T R) / sigma^2 for c columns (T, S: k x c scratch).
-hipError_t pc_apply(const double* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
+hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
                     const float* R, int64_t ldr, int c, double* part, double* T, double* S,
                     float* Z, int64_t ldz, double s2, hipStream_t st);
 // FP64 H[I, I] for every contiguous block of b rows, lower triangle, padded to P x P.

@@ -13,8 +13,11 @@
 //                  FP64 MFMA, a tiled Cholesky (kchol) and k/4 triangular solves
 //                  against identity columns.
 //   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), both skinny
-//                  products on FP64 MFMA with FP64 accumulation; the subtraction
-//                  cancels most of R, which is why nothing here is below FP64.
+//                  products LDS-tiled on FP64 MFMA with FP64 accumulation; the
+//                  subtraction cancels most of R, which is why the arithmetic
+//                  is FP64.  The products read an FP32 copy of the factor (the
+//                  preconditioner is P = L~ L~^T + sigma^2 I for that copy L~,
+//                  Gram matrix included, so P stays exactly SPD).
 //
 // L is stored transposed, L[t * ldl + i] (row t = factor column t), so that both
 // the construction's per-row dot products and the MFMA operand loads are
@@ -145,46 +148,81 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
   }
 }
 
-// part[z][a][b] = sum over rows i of chunk z of L[a][i] * Bop(i, b), a < ka, b < nb,
-// with Bop(i, b) = B[i * brs + b * bcs].  One wave: 16 factor rows a x 16*NBT
-// columns b, v_mfma_f64_16x16x4f64 over 4 rows i per instruction
-// (A lane: L[a0 + l%16][i + l/16]; B lane: Bop(i + l/16, b0 + l%16);
-//  D lane q: (a0 + 4q + l/16, b0 + l%16)).
-template <int NBT, typename TB>
-__global__ __launch_bounds__(256) void kpc_tn(const double* __restrict__ L, int64_t ldl, int ka,
-                                              int64_t n, const TB* __restrict__ B, int64_t brs,
-                                              int64_t bcs, int nb, int64_t csize,
+// part[z][a][b] = sum over rows i of chunk z of L[a][i] * Bop(i, b) for a < ka,
+// b < nb, with L the FP32 copy of the factor ([ka][ldl]) and
+//   BMODE 0: Bop(i, b) = R[i * ldr + b]   (FP32 row-major solver vectors)
+//   BMODE 1: Bop(i, b) = L[b * ldl + i]   (the factor itself: the Gram matrix).
+// One workgroup: a 64 (a) x 16*NBT (b) tile; tiles of 32 rows i are staged in
+// LDS as FP64 and every wave runs v_mfma_f64_16x16x4f64 on 16 a-rows x NBT
+// column tiles (A lane: L[a0 + 16w + l%16][i + 4s + l/16]; B lane:
+// Bop(i + 4s + l/16, b0 + 16u + l%16); D lane q: (a0 + 16w + 4q + l/16,
+// b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.
+constexpr int kTI = 32;  // rows i per LDS stage
+
+template <int NBT, int BMODE>
+__global__ __launch_bounds__(256) void kpc_tn(const float* __restrict__ L, int64_t ldl, int ka,
+                                              int64_t n, const float* __restrict__ R,
+                                              int64_t ldr, int nb, int64_t csize,
                                               double* __restrict__ part) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int a0 = (blockIdx.x * 4 + wave) * 16;
-  const int b0 = blockIdx.y * 16 * NBT;
+  constexpr int NB = 16 * NBT;
+  __shared__ double As[64][kTI + 1];
+  __shared__ double Bs[kTI][NB + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int la = lane & 15, lk = lane >> 4;
+  const int a0 = blockIdx.x * 64;
+  const int b0 = blockIdx.y * NB;
   const int64_t i0 = (int64_t)blockIdx.z * csize;
   const int64_t i1 = i0 + csize < n ? i0 + csize : n;
-  const int la = lane & 15, lk = lane >> 4;
   f64x4 acc[NBT];
 #pragma unroll
-  for (int t = 0; t < NBT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int a = a0 + la;
-  for (int64_t i = i0; i < i1; i += 4) {
-    const int64_t ii = i + lk;
-    const bool rok = ii < i1;
-    const double av = (a < ka && rok) ? L[(int64_t)a * ldl + ii] : 0.0;
+  for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // loader coordinates: 4 threads per 32-float row segment, 8 floats each
+  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  for (int64_t i = i0; i < i1; i += kTI) {
+    {
+      const int a = a0 + lr;
 #pragma unroll
-    for (int t = 0; t < NBT; ++t) {
-      const int b = b0 + 16 * t + la;
-      const double bv = (b < nb && rok) ? (double)B[ii * brs + (int64_t)b * bcs] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        const int64_t ii = i + lc + e;
+        As[lr][lc + e] = (a < ka && ii < i1) ? (double)L[(int64_t)a * ldl + ii] : 0.0;
+      }
     }
-  }
-  if (a0 >= ka) return;
+    if (BMODE == 0) {
+      for (int e = tid; e < kTI * NB; e += 256) {
+        const int r = e / NB, cc = e % NB;
+        const int64_t ii = i + r;
+        const int bcol = b0 + cc;
+        Bs[r][cc] = (ii < i1 && bcol < nb) ? (double)R[ii * ldr + bcol] : 0.0;
+      }
+    } else {
+      for (int rr = lr; rr < NB; rr += 64) {
+        const int bcol = b0 + rr;
 #pragma unroll
-  for (int t = 0; t < NBT; ++t)
+        for (int e = 0; e < 8; ++e) {
+          const int64_t ii = i + lc + e;
+          Bs[lc + e][rr] = (bcol < nb && ii < i1) ? (double)L[(int64_t)bcol * ldl + ii] : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < kTI / 4; ++s4) {
+      const double av = As[16 * wave + la][4 * s4 + lk];
+#pragma unroll
+      for (int u = 0; u < NBT; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[4 * s4 + lk][16 * u + la], acc[u], 0,
+                                                      0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NBT; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ar = a0 + 4 * q + lk;
-      const int bc = b0 + 16 * t + la;
-      if (ar < ka && bc < nb) part[((int64_t)blockIdx.z * ka + ar) * nb + bc] = acc[t][q];
+      const int ar = a0 + 16 * wave + 4 * q + lk;
+      const int bc = b0 + 16 * u + la;
+      if (ar < ka && bc < nb) part[((int64_t)blockIdx.z * ka + ar) * nb + bc] = acc[u][q];
     }
 }
 
@@ -275,42 +313,72 @@ __global__ void kpc_small(const double* __restrict__ M, int kp, const double* __
   S[e] = v;
 }
 
-// Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2.  One wave: 16 rows i x
-// 16*NBT columns, FP64 MFMA over 4 factor columns t per instruction
-// (A lane: L[t + l/16][i0 + l%16]; B lane: S[t + l/16][c0 + l%16]).
+// Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2 with L the FP32 factor
+// copy.  One workgroup: 64 rows i x 16*NBT columns; tiles of 32 factor columns t
+// are staged in LDS as FP64 (A lane: L[t + 4s + l/16][i0 + 16w + l%16]; B lane:
+// S[t + 4s + l/16][c0 + 16u + l%16]; D lane q: (i0 + 16w + 4q + l/16,
+// c0 + 16u + l%16)).
 template <int NBT>
-__global__ __launch_bounds__(256) void kpc_apply(const double* __restrict__ L, int64_t ldl, int k,
+__global__ __launch_bounds__(256) void kpc_apply(const float* __restrict__ L, int64_t ldl, int k,
                                                  int64_t n, const double* __restrict__ S, int nb,
                                                  const float* __restrict__ R, int64_t ldr,
                                                  float* __restrict__ Z, int64_t ldz, double s2) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  const int c0 = blockIdx.y * 16 * NBT;
+  constexpr int NB = 16 * NBT;
+  __shared__ double As[kTI][64 + 1];
+  __shared__ double Bs[kTI][NB + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int la = lane & 15, lk = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * NB;
   f64x4 acc[NBT];
 #pragma unroll
-  for (int t = 0; t < NBT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int64_t ia = i0 + la;
-  for (int t0 = 0; t0 < k; t0 += 4) {
-    const int t = t0 + lk;
-    const double av = (t < k && ia < n) ? L[(int64_t)t * ldl + ia] : 0.0;
+  for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // loader: 8 threads per 64-float row segment of the factor, 8 floats each
+  const int lr = tid >> 3, lc = (tid & 7) * 8;
+  for (int t0 = 0; t0 < k; t0 += kTI) {
+    {
+      const int t = t0 + lr;
 #pragma unroll
-    for (int u = 0; u < NBT; ++u) {
-      const int c = c0 + 16 * u + la;
-      const double bv = (t < k && c < nb) ? S[(int64_t)t * nb + c] : 0.0;
-      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        const int64_t ii = i0 + lc + e;
+        As[lr][lc + e] = (t < k && ii < n) ? (double)L[(int64_t)t * ldl + ii] : 0.0;
+      }
     }
+    for (int e = tid; e < kTI * NB; e += 256) {
+      const int r = e / NB, cc = e % NB;
+      const int t = t0 + r, col = c0 + cc;
+      Bs[r][cc] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < kTI / 4; ++s4) {
+      const double av = As[4 * s4 + lk][16 * wave + la];
+#pragma unroll
+      for (int u = 0; u < NBT; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[4 * s4 + lk][16 * u + la], acc[u], 0,
+                                                      0, 0);
+    }
+    __syncthreads();
   }
   const double inv = 1.0 / s2;
 #pragma unroll
   for (int u = 0; u < NBT; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t i = i0 + 4 * q + lk;
+      const int64_t i = i0 + 16 * wave + 4 * q + lk;
       const int c = c0 + 16 * u + la;
       if (i < n && c < nb) Z[i * ldz + c] = (float)(((double)R[i * ldr + c] - acc[u][q]) * inv);
     }
+}
+
+// FP32 copy of the factor (rows >= n of each factor column set to zero).
+__global__ void kpc_to_f32(const double* __restrict__ L, int64_t ldl, int k, int64_t n,
+                           float* __restrict__ L32) {
+  const int64_t e = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  if (e >= (int64_t)k * ldl) return;
+  const int64_t i = e % ldl;
+  L32[e] = i < n ? (float)L[e] : 0.f;
 }
 
 int blocks_of(int64_t count) { return (int)((count + kPcThreads - 1) / kPcThreads); }
@@ -345,7 +413,15 @@ static int64_t chunk_rows(int64_t n, int64_t tiles, int64_t target) {
   return cs < 64 ? 64 : cs;
 }
 
-hipError_t pc_gram(const double* L, int64_t ldl, int k, int64_t n, double* part,
+hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32,
+                     hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kpc_to_f32, dim3(blocks_of((int64_t)k * ldl)), dim3(kPcThreads), 0, st, L,
+                     ldl, k, n, L32);
+  return hipGetLastError();
+}
+
+hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
                    int64_t part_cap, double* A, int kp, double s2, hipStream_t st) {
   const int64_t xt = (k + 63) / 64, yt = (k + 63) / 64;
   int64_t cs = chunk_rows(n, xt * yt, 2048);
@@ -355,8 +431,8 @@ hipError_t pc_gram(const double* L, int64_t ldl, int k, int64_t n, double* part,
     nz = (n + cs - 1) / cs;
   }
   if (k > 0 && n > 0)
-    hipLaunchKernelGGL((kpc_tn<4, double>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, L,
-                       (int64_t)1, ldl, k, cs, part);
+    hipLaunchKernelGGL((kpc_tn<4, 1>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n,
+                       (const float*)nullptr, (int64_t)0, k, cs, part);
   hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
                      (int)((k > 0 && n > 0) ? nz : 0), k, k, A, kp, kp, s2, 1);
   return hipGetLastError();
@@ -379,15 +455,15 @@ int64_t pc_apply_parts(int64_t n, int k, int c) {
   return ((n + cs - 1) / cs) * (int64_t)k * c;
 }
 
-hipError_t pc_apply(const double* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
+hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
                     const float* R, int64_t ldr, int c, double* part, double* T, double* S,
                     float* Z, int64_t ldz, double s2, hipStream_t st) {
   if (k > 0 && n > 0) {
     const int64_t xt = (k + 63) / 64, yt = (c + 79) / 80;
     const int64_t cs = chunk_rows(n, xt * yt, 2048);
     const int64_t nz = (n + cs - 1) / cs;
-    hipLaunchKernelGGL((kpc_tn<5, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R,
-                       ldr, (int64_t)1, c, cs, part);
+    hipLaunchKernelGGL((kpc_tn<5, 0>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R, ldr,
+                       c, cs, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz, k, c, T, c, 0, 0.0, 0);
     hipLaunchKernelGGL(kpc_small, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, M, kp,

@@ -26,7 +26,7 @@ enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
-  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_COUNT
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -409,7 +409,8 @@ struct Precond {
   int kp = 0;        // k rounded up to 32 (Cholesky / inverse tile)
   int64_t ldl = 0;   // leading dimension of the transposed factor L[t * ldl + i]
   int64_t n = 0;
-  double* L = nullptr;
+  double* L = nullptr;  // FP64 factor from the construction
+  float* L32 = nullptr;  // FP32 copy used by the products (defines P)
   double* M = nullptr;
   double s2 = 0.0;
   bool active = false;
@@ -460,6 +461,8 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   CHK(pc_construct(ctx, X, n, d, theta, k, pc.L, pc.ldl, piv, &pc.k));
   if (pc.k == 0) return GP_OK;
   pc.kp = (int)round_up(pc.k, 32);
+  CHK(ensure(ctx, B_PCL32, (size_t)pc.k * pc.ldl, &pc.L32));
+  HIPCHK(pc_to_f32(pc.L, pc.ldl, pc.k, n, pc.L32, ctx->stream));
   double *part, *A;
   int* stat;
   const int64_t pcap = pc_gram_parts(n, pc.k);
@@ -468,7 +471,7 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   CHK(ensure(ctx, B_PCM, (size_t)pc.kp * pc.kp, &pc.M));
   CHK(ensure(ctx, B_PCSTAT, 1, &stat));
   HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
-  HIPCHK(pc_gram(pc.L, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
+  HIPCHK(pc_gram(pc.L32, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
   HIPCHK(ap_cholesky(A, 1, pc.kp, stat, ctx->stream));
   HIPCHK(pc_inverse(A, pc.kp, pc.M, ctx->stream));
   int hst = 0;
@@ -490,7 +493,7 @@ int pc_apply_cols(gp_ctx* ctx, const Precond& pc, const float* R, int64_t ldr, i
     CHK(ensure(ctx, B_PCS, (size_t)pc.k * c, &S));
   }
   ProfScope ps(ctx, 5);
-  HIPCHK(pc_apply(pc.L, pc.ldl, pc.k, pc.n, pc.M, pc.kp, R, ldr, c, part, T, S, Z, ldz, pc.s2,
+  HIPCHK(pc_apply(pc.L32, pc.ldl, pc.k, pc.n, pc.M, pc.kp, R, ldr, c, part, T, S, Z, ldz, pc.s2,
                   ctx->stream));
   return GP_OK;
 }
