@@ -147,7 +147,7 @@ typedef struct gp_solver_cfg {
   uint64_t sgd_seed;
   int precond_rank;     /* CG only: rank k of the pivoted-Cholesky preconditioner
                            P = L L^T + sigma^2 I (App. B uses 100); 0 = none (P = I);
-                           at most 2016 and capped at n                             */
+                           at most 4096 and capped at n                             */
 } gp_solver_cfg;
 
 typedef struct gp_solve_stats {
@@ -194,7 +194,7 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
  *   piv DEVICE [k] int32 pivot indices (first *rank written)
  *   rank HOST out: the rank reached (<= min(k, n))
  * k = 0 or n = 0 is a no-op with *rank = 0.
- * Errors: GP_ERR_INVALID_ARG (k > 2016, ldl < n, NULL pointers), GP_ERR_HIP. */
+ * Errors: GP_ERR_INVALID_ARG (k > 4096, ldl < n, NULL pointers), GP_ERR_HIP. */
 int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
                         int k, double* L, int64_t ldl, int32_t* piv, int* rank);
 

@@ -219,7 +219,7 @@ struct PcState {
   int rank;
   double dp;
 };
-constexpr int kMaxPrecondRank = 2016;  // padded rank limit (explicit inverse in LDS)
+constexpr int kMaxPrecondRank = 4096;  // padded rank limit (one inverse column in LDS)
 int pc_parts(int64_t n);
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
 // One pivoted-Cholesky step j of k (column j for the current pivot, then the next pivot).
@@ -232,8 +232,11 @@ hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32,
 hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
                    int64_t part_cap, double* A, int kp, double s2, hipStream_t st);
 int64_t pc_gram_parts(int64_t n, int k);
-// M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank).
-hipError_t pc_inverse(const double* C, int kp, double* M, hipStream_t st);
+// M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank,
+// a multiple of 32); W (kp x kp) and part (pc_inverse_parts) are scratch.
+hipError_t pc_inverse(const double* C, int kp, double* W, double* part, int64_t part_cap,
+                      double* M, hipStream_t st);
+int64_t pc_inverse_parts(int kp);
 int64_t pc_apply_parts(int64_t n, int k, int c);
 // Z = (R - L M L^T R) / sigma^2 for c columns (T, S: k x c scratch).
 hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,

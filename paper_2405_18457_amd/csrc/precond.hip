@@ -10,8 +10,9 @@
 //                  host round trips.  Kernel columns are evaluated in FP64 from
 //                  the raw inputs.
 //   inverse        M = (sigma^2 I + L^T L)^-1 (k x k, FP64): the Gram matrix on
-//                  FP64 MFMA, a tiled Cholesky (kchol) and k/4 triangular solves
-//                  against identity columns.
+//                  FP64 MFMA, a tiled Cholesky (kchol), the triangular inverse
+//                  W = C^-1 by panelled forward substitution (one workgroup per
+//                  column) and M = W^T W on FP64 MFMA.
 //   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), both skinny
 //                  products LDS-tiled on FP64 MFMA with FP64 accumulation; the
 //                  subtraction cancels most of R, which is why the arithmetic
@@ -159,8 +160,8 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
 // b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.
 constexpr int kTI = 32;  // rows i per LDS stage
 
-template <int NBT, int BMODE>
-__global__ __launch_bounds__(256) void kpc_tn(const float* __restrict__ L, int64_t ldl, int ka,
+template <int NBT, int BMODE, typename TL>
+__global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
                                               int64_t n, const float* __restrict__ R,
                                               int64_t ldr, int nb, int64_t csize,
                                               double* __restrict__ part) {
@@ -252,54 +253,46 @@ __global__ void kpc_sum(const double* __restrict__ part, int nz, int ka, int nb,
   }
 }
 
-// Columns c0..c0+3 of M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp):
-// forward and backward substitution against identity columns.
-__global__ __launch_bounds__(256) void kpc_inverse(const double* __restrict__ C, int kp,
-                                                   double* __restrict__ M) {
-  constexpr int CW = 4;
-  __shared__ double y[kMaxPrecondRank][CW];
-  __shared__ double red[4][CW];
-  const int c0 = blockIdx.x * CW;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Column a of W = C^-1 for the lower Cholesky factor C (kp x kp, kp a multiple of
+// 32), stored transposed: W[a * kp + i] = (C^-1)[i][a].  Forward substitution on
+// e_a in panels of 32 rows: the rows of a panel first subtract the finished part
+// of the column (coalesced row segments of C, one wave per 8 rows), then wave 0
+// solves the panel's 32 x 32 diagonal block with lane shuffles.  Rows above a's
+// panel stay zero.  M = W^T W is then a product on the matrix cores.
+__global__ __launch_bounds__(256) void kpc_trinv(const double* __restrict__ C, int kp,
+                                                 double* __restrict__ W) {
+  __shared__ double y[kMaxPrecondRank];
+  const int a = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < kp * CW; e += 256) {
-    const int i = e / CW, q = e % CW;
-    y[i][q] = (i == c0 + q) ? 1.0 : 0.0;
-  }
+  const int pa = a & ~31;
+  for (int i = tid; i < kp; i += 256) y[i] = (i == a) ? 1.0 : 0.0;
   __syncthreads();
-  for (int k = 0; k < kp; ++k) {
-    double acc[CW] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = tid; j < k; j += 256) {
-      const double l = C[(int64_t)k * kp + j];
-#pragma unroll
-      for (int q = 0; q < CW; ++q) acc[q] += l * y[j][q];
-    }
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      double v = acc[q];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) red[wave][q] = v;
+  for (int r0 = pa; r0 < kp; r0 += 32) {
+    for (int rr = 0; rr < 8; ++rr) {
+      const int r = r0 + wave * 8 + rr;
+      double acc = 0.0;
+      for (int j = pa + lane; j < r0; j += 64) acc += C[(int64_t)r * kp + j] * y[j];
+      acc = wave_sum(acc);
+      if (lane == 0) y[r] -= acc;
     }
     __syncthreads();
-    if (tid < CW) {
-      const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-      y[k][tid] = (y[k][tid] - s) / C[(int64_t)k * kp + k];
-    }
-    __syncthreads();
-  }
-  for (int k = kp - 1; k >= 0; --k) {
-    if (tid < CW) y[k][tid] /= C[(int64_t)k * kp + k];
-    __syncthreads();
-    for (int j = tid; j < k; j += 256) {
-      const double l = C[(int64_t)k * kp + j];
-#pragma unroll
-      for (int q = 0; q < CW; ++q) y[j][q] -= l * y[k][q];
+    if (wave == 0) {
+      double v = lane < 32 ? y[r0 + lane] : 0.0;
+      for (int m = 0; m < 32; ++m) {
+        const double ym = __shfl(v, m, 64) / C[(int64_t)(r0 + m) * kp + r0 + m];
+        if (lane == m) v = ym;
+        if (lane > m && lane < 32) v -= C[(int64_t)(r0 + lane) * kp + r0 + m] * ym;
+      }
+      if (lane < 32) y[r0 + lane] = v;
     }
     __syncthreads();
   }
-  for (int e = tid; e < kp * CW; e += 256) {
-    const int i = e / CW, q = e % CW;
-    if (c0 + q < kp) M[(int64_t)i * kp + c0 + q] = y[i][q];
-  }
+  for (int i = tid; i < kp; i += 256) W[(int64_t)a * kp + i] = y[i];
 }
 
 // S[a][b] = sum_t M[a][t] T[t][b], a < k, b < nb (M has leading dimension kp).
@@ -431,7 +424,7 @@ hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
     nz = (n + cs - 1) / cs;
   }
   if (k > 0 && n > 0)
-    hipLaunchKernelGGL((kpc_tn<4, 1>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n,
+    hipLaunchKernelGGL((kpc_tn<4, 1, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n,
                        (const float*)nullptr, (int64_t)0, k, cs, part);
   hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
                      (int)((k > 0 && n > 0) ? nz : 0), k, k, A, kp, kp, s2, 1);
@@ -444,10 +437,29 @@ int64_t pc_gram_parts(int64_t n, int k) {
   return ((n + cs - 1) / cs) * (int64_t)k * k;
 }
 
-hipError_t pc_inverse(const double* C, int kp, double* M, hipStream_t st) {
-  if (kp > kMaxPrecondRank) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kpc_inverse, dim3((kp + 3) / 4), dim3(256), 0, st, C, kp, M);
+hipError_t pc_inverse(const double* C, int kp, double* W, double* part, int64_t part_cap,
+                      double* M, hipStream_t st) {
+  if (kp > kMaxPrecondRank || kp % 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kpc_trinv, dim3(kp), dim3(256), 0, st, C, kp, W);
+  // M = W^T W: with W stored transposed, M[a][b] = sum_i W[a][i] W[b][i]
+  const int64_t xt = (kp + 63) / 64;
+  int64_t cs = chunk_rows(kp, xt * xt, 2048);
+  int64_t nz = (kp + cs - 1) / cs;
+  while (nz * (int64_t)kp * kp > part_cap) {
+    cs *= 2;
+    nz = (kp + cs - 1) / cs;
+  }
+  hipLaunchKernelGGL((kpc_tn<4, 1, double>), dim3(xt, xt, nz), dim3(256), 0, st, W, (int64_t)kp,
+                     kp, (int64_t)kp, (const float*)nullptr, (int64_t)0, kp, cs, part);
+  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
+                     (int)nz, kp, kp, M, kp, 0, 0.0, 0);
   return hipGetLastError();
+}
+
+int64_t pc_inverse_parts(int kp) {
+  const int64_t xt = (kp + 63) / 64;
+  const int64_t cs = chunk_rows(kp, xt * xt, 2048);
+  return ((kp + cs - 1) / cs) * (int64_t)kp * kp;
 }
 
 int64_t pc_apply_parts(int64_t n, int k, int c) {
@@ -462,7 +474,7 @@ hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double*
     const int64_t xt = (k + 63) / 64, yt = (c + 79) / 80;
     const int64_t cs = chunk_rows(n, xt * yt, 2048);
     const int64_t nz = (n + cs - 1) / cs;
-    hipLaunchKernelGGL((kpc_tn<5, 0>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R, ldr,
+    hipLaunchKernelGGL((kpc_tn<5, 0, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R, ldr,
                        c, cs, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz, k, c, T, c, 0, 0.0, 0);

@@ -26,7 +26,7 @@ enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
-  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_COUNT
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -473,7 +473,11 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
   HIPCHK(pc_gram(pc.L32, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
   HIPCHK(ap_cholesky(A, 1, pc.kp, stat, ctx->stream));
-  HIPCHK(pc_inverse(A, pc.kp, pc.M, ctx->stream));
+  double* W;
+  CHK(ensure(ctx, B_PCW, (size_t)pc.kp * pc.kp, &W));
+  const int64_t icap = pc_inverse_parts(pc.kp);
+  if (icap > pcap) CHK(ensure(ctx, B_PCPART, (size_t)icap, &part));
+  HIPCHK(pc_inverse(A, pc.kp, W, part, std::max(icap, pcap), pc.M, ctx->stream));
   int hst = 0;
   HIPCHK(hipMemcpyAsync(ctx->hpin, stat, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));

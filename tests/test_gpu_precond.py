@@ -91,7 +91,7 @@ def test_precond_rank_validation(gp):
     X, B, theta = problem(100, 3, 3, seed=5)
     U = torch.zeros((100, 3), device="cuda")
     with pytest.raises(api.GPError):
-        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(precond_rank=3000))
+        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(precond_rank=5000))
     with pytest.raises(api.GPError):
         api.gp_solve(gp, dev(X), theta, dev(B), U,
                      api.solver_cfg(solver=api.GP_AP, precond_rank=10, ap_block=50))
