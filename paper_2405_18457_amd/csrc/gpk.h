@@ -222,10 +222,11 @@ struct PcState {
 constexpr int kMaxPrecondRank = 4096;  // padded rank limit (one inverse column in LDS)
 int pc_parts(int64_t n);
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
-// One pivoted-Cholesky step j of k (column j for the current pivot, then the next pivot).
+// One pivoted-Cholesky step j of k (column j for the current pivot, then the next
+// pivot); the factor is FP32 in L32 when L32 is non-null, else FP64 in L.
 hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a2, double* L,
-                   int64_t ldl, int j, int k, double* diag, PcState* s, double* lp, double* pval,
-                   int64_t* pidx, int32_t* piv, hipStream_t st);
+                   float* L32, int64_t ldl, int j, int k, double* diag, PcState* s, double* lp,
+                   double* pval, int64_t* pidx, int32_t* piv, hipStream_t st);
 // FP32 copy of the factor, used by the products below.
 hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32, hipStream_t st);
 // A (kp x kp) = sigma^2 I + L^T L on the leading k x k block, identity elsewhere.
@@ -247,6 +248,9 @@ hipError_t ap_build_blocks(const float* xp, int DP, int d, int64_t n, int b, int
                            double s2, double* M, hipStream_t st);
 // In-place lower Cholesky of nblk P x P blocks; status bit 2 on a non-positive pivot.
 hipError_t ap_cholesky(double* M, int nblk, int P, int* status, hipStream_t st);
+// In-place lower Cholesky of one large P x P matrix (P a multiple of 32) over many
+// workgroups; status bit 2 on a non-positive pivot.
+hipError_t chol_blocked(double* A, int P, int* status, hipStream_t st);
 // out[i, :c] = H[I_blk, I_blk]^-1 R[I_blk, :c] from the cached factor.
 hipError_t ap_solve_block(const double* M, int P, int blk, int b, int64_t n, const float* R,
                           int64_t ldr, int c, float* out, int64_t ldo, hipStream_t st);

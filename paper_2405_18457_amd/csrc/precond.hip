@@ -8,7 +8,9 @@
 //                  d <- d - l_j^2.  Two launches per step (column + pivot);
 //                  the pivot stays in device memory, so the k steps run without
 //                  host round trips.  Kernel columns are evaluated in FP64 from
-//                  the raw inputs.
+//                  the raw inputs.  The solver's preconditioner keeps the factor
+//                  in FP32 (the dot products with earlier columns read half the
+//                  bytes; sums stay FP64); gp_pivoted_cholesky keeps it in FP64.
 //   inverse        M = (sigma^2 I + L^T L)^-1 (k x k, FP64): the Gram matrix on
 //                  FP64 MFMA, a tiled Cholesky (kchol), the triangular inverse
 //                  W = C^-1 by panelled forward substitution (one workgroup per
@@ -73,44 +75,89 @@ __device__ void block_argmax(double v, int64_t i, double* sv, int64_t* si, doubl
 }
 
 // Step j: factor column j for pivot s->p, diagonal update, per-block argmax.
+// Each thread owns kPcRows consecutive rows, so the dot products with the
+// previous factor columns run as kPcRows independent FP64 chains fed by one
+// vector load per column.  F32: the factor is kept only as FP32 (L32), which
+// halves the bytes these dot products read (products and sums stay FP64);
+// otherwise the factor is FP64 (L) throughout.
+constexpr int kPcRows = 4;
+
+template <bool F32>
 __global__ __launch_bounds__(kPcThreads) void kpc_column(
     const float* __restrict__ X, int64_t n, int d, const double* __restrict__ ell, double a2,
-    double* __restrict__ L, int64_t ldl, int j, double* __restrict__ diag,
-    const PcState* __restrict__ s, const double* __restrict__ lp, double* __restrict__ pval,
-    int64_t* __restrict__ pidx) {
+    double* __restrict__ L, float* __restrict__ L32, int64_t ldl, int j,
+    double* __restrict__ diag, const PcState* __restrict__ s, const double* __restrict__ lp,
+    double* __restrict__ pval, int64_t* __restrict__ pidx) {
   __shared__ double sv[kPcThreads];
   __shared__ int64_t si[kPcThreads];
-  const int64_t i = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  const int64_t i0 = ((int64_t)blockIdx.x * kPcThreads + threadIdx.x) * kPcRows;
   const int64_t p = s->p;
   const double dp = s->dp;
   const bool stop = s->stop != 0;
   double nd = 0.0;
   int64_t ni = -1;
-  if (!stop && i < n) {
-    double r2 = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double t = (double)X[i * d + k] / ell[k] - (double)X[p * d + k] / ell[k];
-      r2 += t * t;
+  if (!stop && i0 < n) {
+    double kv[kPcRows];
+#pragma unroll
+    for (int q = 0; q < kPcRows; ++q) {
+      const int64_t i = i0 + q < n ? i0 + q : n - 1;
+      double r2 = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double t = (double)X[i * d + k] / ell[k] - (double)X[p * d + k] / ell[k];
+        r2 += t * t;
+      }
+      const double r = sqrt(3.0 * r2);
+      kv[q] = a2 * (1.0 + r) * exp(-r);
     }
-    const double r = sqrt(3.0 * r2);
-    double kv = a2 * (1.0 + r) * exp(-r);
-    for (int t = 0; t < j; ++t) kv -= L[(int64_t)t * ldl + i] * lp[t];
-    const double l = kv / sqrt(dp);
-    L[(int64_t)j * ldl + i] = l;
-    double di = diag[i] - l * l;
-    if (i == p) di = 0.0;
-    diag[i] = di;
-    nd = di;
-    ni = i;
+    // F32: ldl is a multiple of kPcRows, so the vector loads stay inside each
+    // factor column (rows >= n load unused values that are never stored)
+    if (F32) {
+#pragma unroll 8
+      for (int t = 0; t < j; ++t) {
+        const float4 v = *reinterpret_cast<const float4*>(L32 + (int64_t)t * ldl + i0);
+        const double w = lp[t];
+        kv[0] -= (double)v.x * w;
+        kv[1] -= (double)v.y * w;
+        kv[2] -= (double)v.z * w;
+        kv[3] -= (double)v.w * w;
+      }
+    } else {
+      for (int t = 0; t < j; ++t) {
+        const double w = lp[t];
+#pragma unroll
+        for (int q = 0; q < kPcRows; ++q)
+          if (i0 + q < n) kv[q] -= L[(int64_t)t * ldl + i0 + q] * w;
+      }
+    }
+    const double inv = 1.0 / sqrt(dp);
+#pragma unroll
+    for (int q = 0; q < kPcRows; ++q) {
+      const int64_t i = i0 + q;
+      if (i >= n) break;
+      const double l = kv[q] * inv;
+      if (F32)
+        L32[(int64_t)j * ldl + i] = (float)l;
+      else
+        L[(int64_t)j * ldl + i] = l;
+      double di = diag[i] - l * l;
+      if (i == p) di = 0.0;
+      diag[i] = di;
+      if (better(di, i, nd, ni)) {
+        nd = di;
+        ni = i;
+      }
+    }
   }
   block_argmax(nd, ni, sv, si, pval + blockIdx.x, pidx + blockIdx.x);
 }
 
 // After step j: the next pivot from the block maxima, its remaining diagonal and
 // its factor row L[p, :j+1] (gathered for the next step's dot products).
+template <bool F32>
 __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict__ pval,
                                                         const int64_t* __restrict__ pidx,
                                                         int nparts, const double* __restrict__ L,
+                                                        const float* __restrict__ L32,
                                                         int64_t ldl, int j, int k,
                                                         PcState* __restrict__ s,
                                                         double* __restrict__ lp,
@@ -136,7 +183,8 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
     return;
   }
   if (bi >= 0 && bv > 0.0) {
-    for (int t = threadIdx.x; t <= j; t += kPcThreads) lp[t] = L[(int64_t)t * ldl + bi];
+    for (int t = threadIdx.x; t <= j; t += kPcThreads)
+      lp[t] = F32 ? (double)L32[(int64_t)t * ldl + bi] : L[(int64_t)t * ldl + bi];
     if (threadIdx.x == 0) {
       s->rank = j + 1;
       s->p = bi;
@@ -378,7 +426,7 @@ int blocks_of(int64_t count) { return (int)((count + kPcThreads - 1) / kPcThread
 
 }  // namespace
 
-int pc_parts(int64_t n) { return blocks_of(n); }
+int pc_parts(int64_t n) { return blocks_of((n + kPcRows - 1) / kPcRows); }
 
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st) {
   hipLaunchKernelGGL(kpc_init, dim3(blocks_of(n > 0 ? n : 1)), dim3(kPcThreads), 0, st, diag, n,
@@ -387,13 +435,21 @@ hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv,
 }
 
 hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a2, double* L,
-                   int64_t ldl, int j, int k, double* diag, PcState* s, double* lp, double* pval,
-                   int64_t* pidx, int32_t* piv, hipStream_t st) {
-  const int nparts = blocks_of(n);
-  hipLaunchKernelGGL(kpc_column, dim3(nparts), dim3(kPcThreads), 0, st, X, n, d, ell, a2, L, ldl,
-                     j, diag, s, lp, pval, pidx);
-  hipLaunchKernelGGL(kpc_pivot, dim3(1), dim3(kPcThreads), 0, st, pval, pidx, nparts, L, ldl, j,
-                     k, s, lp, piv);
+                   float* L32, int64_t ldl, int j, int k, double* diag, PcState* s, double* lp,
+                   double* pval, int64_t* pidx, int32_t* piv, hipStream_t st) {
+  if (L32 && ldl % kPcRows) return hipErrorInvalidValue;
+  const int nparts = pc_parts(n);
+  if (L32) {
+    hipLaunchKernelGGL(kpc_column<true>, dim3(nparts), dim3(kPcThreads), 0, st, X, n, d, ell, a2,
+                       L, L32, ldl, j, diag, s, lp, pval, pidx);
+    hipLaunchKernelGGL(kpc_pivot<true>, dim3(1), dim3(kPcThreads), 0, st, pval, pidx, nparts, L,
+                       L32, ldl, j, k, s, lp, piv);
+  } else {
+    hipLaunchKernelGGL(kpc_column<false>, dim3(nparts), dim3(kPcThreads), 0, st, X, n, d, ell,
+                       a2, L, L32, ldl, j, diag, s, lp, pval, pidx);
+    hipLaunchKernelGGL(kpc_pivot<false>, dim3(1), dim3(kPcThreads), 0, st, pval, pidx, nparts, L,
+                       L32, ldl, j, k, s, lp, piv);
+  }
   return hipGetLastError();
 }
 

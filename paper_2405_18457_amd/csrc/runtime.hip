@@ -409,16 +409,16 @@ struct Precond {
   int kp = 0;        // k rounded up to 32 (Cholesky / inverse tile)
   int64_t ldl = 0;   // leading dimension of the transposed factor L[t * ldl + i]
   int64_t n = 0;
-  double* L = nullptr;  // FP64 factor from the construction
-  float* L32 = nullptr;  // FP32 copy used by the products (defines P)
+  float* L32 = nullptr;  // FP32 factor (defines P; the products read it)
   double* M = nullptr;
   double s2 = 0.0;
   bool active = false;
 };
 
-// Greedy construction into L [k, ldl] / piv [k]; returns the rank reached.
+// Greedy construction into L [k, ldl] (FP64) or, when L32 is given, L32 [k, ldl]
+// (FP32); piv [k]; returns the rank reached.
 int pc_construct(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, int k,
-                 double* L, int64_t ldl, int32_t* piv, int* rank) {
+                 double* L, float* L32, int64_t ldl, int32_t* piv, int* rank) {
   *rank = 0;
   if (k <= 0 || n <= 0) return GP_OK;
   double *diag, *lp, *pval, *ell;
@@ -437,7 +437,8 @@ int pc_construct(gp_ctx* ctx, const float* X, int64_t n, int d, const double* th
   const double a2 = theta[d] * theta[d];
   HIPCHK(pc_init(diag, n, a2, st, piv, ctx->stream));
   for (int j = 0; j < k; ++j)
-    HIPCHK(pc_step(X, n, d, ell, a2, L, ldl, j, k, diag, st, lp, pval, pidx, piv, ctx->stream));
+    HIPCHK(pc_step(X, n, d, ell, a2, L, L32, ldl, j, k, diag, st, lp, pval, pidx, piv,
+                   ctx->stream));
   PcState hs;
   HIPCHK(hipMemcpyAsync(ctx->hpin, st, sizeof(PcState), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -456,13 +457,11 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   if (k <= 0) return GP_OK;
   pc.ldl = round_up(n, 64);
   int32_t* piv;
-  CHK(ensure(ctx, B_PCL, (size_t)k * pc.ldl, &pc.L));
+  CHK(ensure(ctx, B_PCL32, (size_t)k * pc.ldl, &pc.L32));
   CHK(ensure(ctx, B_PCPIV, (size_t)k, &piv));
-  CHK(pc_construct(ctx, X, n, d, theta, k, pc.L, pc.ldl, piv, &pc.k));
+  CHK(pc_construct(ctx, X, n, d, theta, k, nullptr, pc.L32, pc.ldl, piv, &pc.k));
   if (pc.k == 0) return GP_OK;
   pc.kp = (int)round_up(pc.k, 32);
-  CHK(ensure(ctx, B_PCL32, (size_t)pc.k * pc.ldl, &pc.L32));
-  HIPCHK(pc_to_f32(pc.L, pc.ldl, pc.k, n, pc.L32, ctx->stream));
   double *part, *A;
   int* stat;
   const int64_t pcap = pc_gram_parts(n, pc.k);
@@ -472,7 +471,7 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   CHK(ensure(ctx, B_PCSTAT, 1, &stat));
   HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
   HIPCHK(pc_gram(pc.L32, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
-  HIPCHK(ap_cholesky(A, 1, pc.kp, stat, ctx->stream));
+  HIPCHK(chol_blocked(A, pc.kp, stat, ctx->stream));
   double* W;
   CHK(ensure(ctx, B_PCW, (size_t)pc.kp * pc.kp, &W));
   const int64_t icap = pc_inverse_parts(pc.kp);
@@ -1077,7 +1076,8 @@ int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const dou
   if (ldl < n) return fail(ctx, GP_ERR_INVALID_ARG, "ldl %lld < n %lld", (long long)ldl,
                            (long long)n);
   HIPCHK(hipSetDevice(ctx->device));
-  return pc_construct(ctx, X, n, d, theta, (int)std::min<int64_t>(k, n), L, ldl, piv, rank);
+  return pc_construct(ctx, X, n, d, theta, (int)std::min<int64_t>(k, n), L, nullptr, ldl, piv,
+                      rank);
 }
 
 int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const double* theta,
