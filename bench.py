@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--precond-rank", type=int, default=4000,
                     help="rank of CG's pivoted-Cholesky preconditioner (the paper uses 100; the "
                          "library allows up to 4096; 0 = none)")
+    ap.add_argument("--probe-scaling", action="store_true",
+                    help="only time the forward product at 1..256 columns on the bench inputs "
+                         "(cost of adding probe vectors)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler against a known traffic)")
@@ -115,6 +118,33 @@ def kernel_only(args):
                       "avg_call_ms": round(1e3 * wall / max(args.kernel_only, 1), 3),
                       "kernel_entries_per_s": float(n) * n / (ms / max(cnt, 1) / 1e3)}),
           flush=True)
+
+
+def probe_scaling(args):
+    """Forward-product time against the number of columns c = s + 1 (the kernel values
+    are computed once per entry and shared by all columns of a 128-column pass)."""
+    import torch
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    inp, _, dev = make_inputs(args.n)
+    n = inp["n"]
+    prec = {"bf16x3": api.GP_BF16X3, "fp32": api.GP_FP32, "bf16": api.GP_BF16}[args.precision]
+    base = None
+    for c in (1, 9, 17, 33, 65, 129, 256):
+        V = dev(np.random.default_rng(c).standard_normal((n, c)).astype(np.float32))
+        out = torch.empty_like(V)
+        api.gp_kmatvec(ctx, inp["X"], inp["X"], inp["theta_true"], V, prec, True, out)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        for _ in range(2):
+            api.gp_kmatvec(ctx, inp["X"], inp["X"], inp["theta_true"], V, prec, True, out)
+        ms, cnt = ctx.profile_read(4 if prec == api.GP_FP32 else 0)
+        ctx.profile_enable(False)
+        per = ms / cnt * (cnt // 2)  # kernel time of one product (all of its column passes)
+        base = per if c == 1 else base
+        print(json.dumps({"probe_scaling": args.precision, "n": n, "columns": c,
+                          "product_ms": round(per, 3), "relative_to_1_column": round(per / base, 3)}),
+              flush=True)
 
 
 def make_inputs(n=None):
@@ -263,6 +293,9 @@ def main():
         return
     if args.kernel_only:
         kernel_only(args)
+        return
+    if args.probe_scaling:
+        probe_scaling(args)
         return
     import torch
     from paper_2405_18457_amd import api

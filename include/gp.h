@@ -214,6 +214,23 @@ int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const d
                     const float* t, int M, const float* W, int64_t ldw, int s, float* F,
                     int64_t ldf);
 
+/* Pathwise posterior samples (Sec. 2 eq. pathwise_conditioning; Sec. 3,
+ * "Amortising Linear Solves for Optimisation and Prediction"): with the pathwise
+ * solutions U = [v_y, zhat_1..zhat_s] of H U = [y, xi_1..xi_s] and the same
+ * random features (t, W) that produced the prior draws xi_j = f_j(x) + eps_j,
+ *   F[q, j] = f_j(Xq[q]) + sum_i k(Xq[q], X[i]) (v_y[i] - zhat_j[i]),
+ * i.e. prediction at Xq without further solves.  f_j is gp_prior_sample's
+ * random-feature function; the kernel product runs at `precision`.
+ *   Xq [m_rows, d] query points; X [n, d] training inputs; t [M, d], W [2M, ldw]
+ *   as in gp_prior_sample (first s columns of W); U [n, ldu] (s + 1 columns:
+ *   v_y, then zhat_1..zhat_s); F [m_rows, ldf] output (first s columns).
+ * n = 0 returns the prior samples; m_rows = 0 or s = 0 is a no-op.
+ * Errors as gp_prior_sample and gp_kmatvec.                                 */
+int gp_posterior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, const float* X, int64_t n,
+                        int d, const double* theta, const float* t, int M, const float* W,
+                        int64_t ldw, const float* U, int64_t ldu, int s, int precision, float* F,
+                        int64_t ldf);
+
 /* -------------------------------------------------- marginal-likelihood step */
 
 /* Gradient estimate of the log marginal likelihood (Sec. 2 eq. mll_grad):

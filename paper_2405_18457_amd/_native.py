@@ -28,6 +28,7 @@ EXPORTS = (
     "gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_profile_enable",
     "gp_profile_read", "gp_kmatvec", "gp_kmatvec_adjoint", "gp_solver_cfg_default", "gp_solve",
     "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_pivoted_cholesky",
+    "gp_posterior_sample",
 )
 
 
@@ -88,6 +89,8 @@ def lib():
             "gp_nu_to_theta": (i32, [i32, pd, i32, pd]),
             "gp_pivoted_cholesky": (i32, [vp, vp, i64, i32, pd, i32, vp, i64, vp,
                                           C.POINTER(C.c_int)]),
+            "gp_posterior_sample": (i32, [vp, vp, i64, vp, i64, i32, pd, vp, i32, vp, i64, vp,
+                                          i64, i32, i32, vp, i64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

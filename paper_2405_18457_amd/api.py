@@ -190,6 +190,27 @@ def gp_prior_sample(ctx: Context, Xq, theta, t, W, out=None):
     return out
 
 
+def gp_posterior_sample(ctx: Context, Xq, X, theta, t, W, U, precision=GP_BF16X3, out=None):
+    """Pathwise posterior samples at Xq from the pathwise solutions U = [v_y, zhat_1..zhat_s]
+    and the random features (t, W) of the prior draws: returns F [m, s]."""
+    m, d = Xq.shape
+    n = X.shape[0]
+    M = t.shape[0]
+    s = _cols(U) - 1
+    if out is None:
+        out = torch.empty((m, s), device=Xq.device, dtype=torch.float32)
+    th, thp = _theta(theta)
+    xq, _ = _dptr(Xq, "Xq")
+    x, _ = _dptr(X, "X")
+    tt, _ = _dptr(t, "t")
+    w, ldw = _dptr(W, "W")
+    u, ldu = _dptr(U, "U")
+    f, ldf = _dptr(out, "out")
+    ctx.check(N.lib().gp_posterior_sample(ctx.handle, xq, m, x, n, d, thp, tt, M, w, ldw, u, ldu,
+                                          s, precision, f, ldf))
+    return out
+
+
 def gp_mll_grad(ctx: Context, X, y, theta, estimator, U, cfg: SolverCfg, Z=None, rff_t=None,
                 rff_W=None, w_eps=None, adjoint_mode=GP_ADJ_FUSED):
     """Returns (grad_theta [d+2], stats); U [n, s+1] is the warm-start / solution buffer."""

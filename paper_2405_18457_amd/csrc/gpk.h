@@ -204,6 +204,8 @@ hipError_t axpy_cols(float* Y, const float* X, int64_t n, int64_t ld, int c, flo
 hipError_t copy_cols(const float* src, int64_t lds, int64_t n, int c, float* dst, int64_t ldd,
                      hipStream_t st);
 hipError_t fill(float* dst, int64_t count, float v, hipStream_t st);
+// D[i][j] = U[i][0] - U[i][1 + j], j < s (D row-major [n, s]).
+hipError_t post_diff(const float* U, int64_t ldu, int64_t n, int s, float* D, hipStream_t st);
 hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* status,
                         hipStream_t st);
 

@@ -26,7 +26,7 @@ enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
-  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_COUNT
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -237,8 +237,13 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
 int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64_t ldv, int cols,
           float* out, int64_t ldo, int prec, float scale, const float* vn, int64_t ldvn,
           float noise, int fn = FN_MATERN, int fn_dim = 0) {
-  for (int c0 = 0; c0 < cols; c0 += 128) {
-    const int cs = std::min(128, cols - c0);
+  // Columns go in balanced passes of at most 80 (5 column tiles with 4 row
+  // sub-tiles per wave): wider single passes (8 tiles, 2 sub-tiles) measured
+  // slower than two such passes, although each pass re-evaluates the kernel.
+  const int npass = (cols + 79) / 80;
+  const int per = (cols + npass - 1) / npass;
+  for (int c0 = 0; c0 < cols; c0 += per) {
+    const int cs = std::min(per, cols - c0);
     const int CT = select_CT(cs);
     FwdArgs a;
     a.prec = prec;
@@ -1122,6 +1127,28 @@ int gp_prior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, int d, const d
   // the pinned buffer held inv_ell for the copy above: wait before it is reused
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP_OK;
+}
+
+int gp_posterior_sample(gp_ctx* ctx, const float* Xq, int64_t m_rows, const float* X, int64_t n,
+                        int d, const double* theta, const float* t, int M, const float* W,
+                        int64_t ldw, const float* U, int64_t ldu, int s, int precision, float* F,
+                        int64_t ldf) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_prec(ctx, precision));
+  CHK(check_dims(ctx, d, s));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "U", U, n, ldu, s + 1));
+  CHK(gp_prior_sample(ctx, Xq, m_rows, d, theta, t, M, W, ldw, s, F, ldf));
+  if (m_rows == 0 || s == 0 || n == 0) return GP_OK;
+  float* Dd;
+  CHK(ensure(ctx, B_POSTD, (size_t)n * s, &Dd));
+  HIPCHK(post_diff(U, ldu, n, s, Dd, ctx->stream));
+  Packed pq, px;
+  CHK(pack_points(ctx, B_XP1, Xq, nullptr, m_rows, d, theta, &pq));
+  CHK(pack_points(ctx, B_XP2, X, nullptr, n, d, theta, &px));
+  // F = a^2 K(Xq, X) D + 1 * F  (the prior samples enter through the epilogue's added term)
+  return kprod(ctx, pq, px, Dd, s, s, F, ldf, precision, a2_of(theta, d), F, ldf, 1.0f);
 }
 
 int gp_mll_grad(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,

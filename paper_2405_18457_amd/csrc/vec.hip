@@ -354,6 +354,16 @@ __global__ void kcopy_cols(const float* __restrict__ src, int64_t lds, int64_t n
   dst[i * ldd + col] = src[i * lds + col];
 }
 
+// D[i][j] = U[i][0] - U[i][1 + j] for j < s (pathwise posterior weights v_y - zhat_j).
+__global__ void kpost_diff(const float* __restrict__ U, int64_t ldu, int64_t n, int s,
+                           float* __restrict__ D) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= n * s) return;
+  const int64_t i = t / s;
+  const int j = (int)(t % s);
+  D[t] = U[i * ldu] - U[i * ldu + 1 + j];
+}
+
 __global__ void kfill(float* __restrict__ dst, int64_t count, float v) {
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t < count) dst[t] = v;
@@ -590,6 +600,11 @@ hipError_t copy_cols(const float* src, int64_t lds, int64_t n, int c, float* dst
   if (n * c == 0) return hipSuccess;
   hipLaunchKernelGGL(kcopy_cols, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, src, lds, n, c,
                      dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t post_diff(const float* U, int64_t ldu, int64_t n, int s, float* D, hipStream_t st) {
+  hipLaunchKernelGGL(kpost_diff, dim3(blocks_for(n * s)), dim3(kThreads), 0, st, U, ldu, n, s, D);
   return hipGetLastError();
 }
 

@@ -1,0 +1,85 @@
+"""Pathwise posterior samples (Sec. 2 eq. pathwise_conditioning, Sec. 3 "Amortising
+Linear Solves for Optimisation and Prediction") on the GPU against the FP64 oracle:
+F = f(Xq) + K(Xq, X)(v_y - zhat) from the same random features and the same
+pathwise solutions."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_common import announce, dev, host, problem, require_gpu
+from oracle import mll, rff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    require_gpu()
+    from paper_2405_18457_amd import api
+    ctx = api.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _setup(n, m, d, s, M, seed):
+    X, _, theta = problem(n, d, 1, seed=seed, dist="uniform", ell_scale=(0.2, 0.5))
+    Xq, _, _ = problem(m, d, 1, seed=seed + 1, dist="uniform")
+    g = np.random.default_rng(seed + 2)
+    t = wl.draw_spectral_t3(g, M, d).astype(np.float32)
+    W = g.standard_normal((2 * M, s)).astype(np.float32)
+    U = g.standard_normal((n, s + 1)).astype(np.float32) * 0.1
+    return X, Xq, theta, t, W, U
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-5), (1, 5e-5)], ids=["fp32", "bf16x3"])
+@pytest.mark.parametrize("n,m,d,s,M", [(1500, 333, 3, 8, 200), (700, 130, 8, 17, 64)])
+def test_posterior_samples_match_oracle(gp, n, m, d, s, M, prec, tol):
+    from paper_2405_18457_amd import api
+    X, Xq, theta, t, W, U = _setup(n, m, d, s, M, seed=n + m)
+    announce("posterior", n, m, d, s, prec)
+    F = host(api.gp_posterior_sample(gp, dev(Xq), dev(X), theta, dev(t), dev(W), dev(U),
+                                     precision=prec))
+    ref = rff.posterior_samples(Xq, X, theta, t, W, U[:, 0], U[:, 1:])
+    err = float(np.linalg.norm(F - ref) / np.linalg.norm(ref))
+    assert err <= tol, err
+
+
+def test_posterior_samples_edge_cases(gp):
+    from paper_2405_18457_amd import api
+    import torch
+    X, Xq, theta, t, W, U = _setup(50, 20, 3, 4, 16, seed=9)
+    # no training points: the prior samples themselves
+    F0 = api.gp_posterior_sample(gp, dev(Xq), dev(X[:0]), theta, dev(t), dev(W), dev(U[:0]))
+    np.testing.assert_allclose(host(F0), rff.prior_sample(Xq, t, W, theta), rtol=1e-4, atol=1e-5)
+    # no query points: nothing to do
+    out = torch.empty((0, 4), device="cuda")
+    api.gp_posterior_sample(gp, dev(Xq[:0]), dev(X), theta, dev(t), dev(W), dev(U), out=out)
+
+
+def test_posterior_samples_from_a_pathwise_solve(gp):
+    """End to end: the pathwise gradient step leaves U = [v_y, zhat]; the posterior
+    samples built from it agree with the oracle's from the same U, and their mean
+    over samples approaches the exact posterior mean."""
+    from paper_2405_18457_amd import api
+    import torch
+    w = wl.WORKLOADS["A"]
+    X = wl.draw_inputs(w)
+    tr = wl.truth_draws(w)
+    y = rff.truth_targets_exact(X, tr["ell"], 1.0, w.sigma, tr["w"], tr["noise"]).astype(np.float32)
+    dr = wl.model_pathwise_draws(w)
+    theta = np.concatenate([tr["ell"], [1.0, w.sigma]])
+    U = torch.zeros((w.n, w.s + 1), device="cuda")
+    cfg = api.solver_cfg(tol=1e-3, precision=api.GP_BF16X3)
+    announce("posterior-e2e")
+    api.gp_mll_grad(gp, dev(X), dev(y), theta, api.GP_PATHWISE, U, cfg, rff_t=dev(dr["t"]),
+                    rff_W=dev(dr["W"]), w_eps=dev(dr["w_eps"]))
+    Xq = X[:200] + np.float32(0.05)
+    F = host(api.gp_posterior_sample(gp, dev(Xq), dev(X), theta, dev(dr["t"]), dev(dr["W"]), U))
+    Uh = host(U)
+    ref = rff.posterior_samples(Xq, X, theta, dr["t"], dr["W"], Uh[:, 0], Uh[:, 1:])
+    assert float(np.linalg.norm(F - ref) / np.linalg.norm(ref)) <= 5e-5
+    # the sample mean estimates the posterior mean k(Xq, X) H^-1 y (s = 16 samples)
+    from oracle import kernel
+    mu = kernel.k_matvec(Xq, X, theta, mll.exact_solve(X, theta, y[:, None].astype(np.float64)))[:, 0]
+    spread = F.std(axis=1).mean()
+    assert np.abs(F.mean(axis=1) - mu).mean() <= 3 * spread / np.sqrt(F.shape[1])
