@@ -148,6 +148,12 @@ typedef struct gp_solver_cfg {
   int precond_rank;     /* CG only: rank k of the pivoted-Cholesky preconditioner
                            P = L L^T + sigma^2 I (App. B uses 100); 0 = none (P = I);
                            at most 4096 and capped at n                             */
+  int use_graph;        /* CG only: run the solve on a library-owned stream (ordered with
+                           the context's stream by events) and replay one captured
+                           iteration as a HIP graph from the second iteration on; the
+                           results are identical to the eager solve. Worth it where an
+                           iteration is short (small n). Per-kernel profiling is not
+                           recorded for replayed iterations.                          */
 } gp_solver_cfg;
 
 typedef struct gp_solve_stats {

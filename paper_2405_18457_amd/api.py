@@ -99,7 +99,8 @@ def _cols(t):
 
 def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine_every=0,
                check_every=0, ap_block=1000, sgd_batch=500, sgd_lr=10.0, sgd_momentum=0.9,
-               sgd_batches: np.ndarray | None = None, sgd_seed=0, precond_rank=0) -> SolverCfg:
+               sgd_batches: np.ndarray | None = None, sgd_seed=0, precond_rank=0,
+               use_graph=False) -> SolverCfg:
     cfg = SolverCfg()
     N.lib().gp_solver_cfg_default(C.byref(cfg))
     cfg.solver, cfg.tol, cfg.max_epochs = solver, tol, max_epochs
@@ -107,6 +108,7 @@ def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine
     cfg.ap_block, cfg.sgd_batch, cfg.sgd_lr, cfg.sgd_momentum = ap_block, sgd_batch, sgd_lr, sgd_momentum
     cfg.sgd_seed = sgd_seed
     cfg.precond_rank = precond_rank
+    cfg.use_graph = int(use_graph)
     if sgd_batches is not None:
         arr = np.ascontiguousarray(sgd_batches, dtype=np.int32)
         cfg._batches_keepalive = arr

@@ -45,6 +45,9 @@ struct Packed {
 struct gp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t gstream = nullptr;  // library-owned stream for captured solver iterations
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  uint64_t alloc_epoch = 0;       // bumped on every workspace (re)allocation
   std::string err;
   void* buf[B_COUNT] = {};
   size_t cap[B_COUNT] = {};
@@ -92,6 +95,7 @@ int ensure(gp_ctx* ctx, BufId id, size_t count, T** out) {
     ctx->buf[id] = nullptr;
     ctx->cap[id] = 0;
     size_t want = bytes + bytes / 8;
+    ++ctx->alloc_epoch;
     if (hipMalloc(&ctx->buf[id], want) != hipSuccess) {
       (void)hipGetLastError();
       ctx->buf[id] = nullptr;
@@ -190,6 +194,8 @@ int check_precond(gp_ctx* ctx, const gp_solver_cfg& cfg) {
                 kMaxPrecondRank);
   if (cfg.precond_rank > 0 && cfg.solver != GP_CG)
     return fail(ctx, GP_ERR_INVALID_ARG, "the pivoted-Cholesky preconditioner is for CG only");
+  if (cfg.use_graph && cfg.solver != GP_CG)
+    return fail(ctx, GP_ERR_INVALID_ARG, "graph-captured iterations are for CG only");
   return GP_OK;
 }
 
@@ -531,9 +537,38 @@ int solve_finish(gp_ctx* ctx, SolveState& s, float* U, int64_t ldu) {
   return GP_OK;
 }
 
+// Runs the solve on the library's own (capturable) stream, ordered after and
+// before the caller's stream with events; restores the caller's stream on exit.
+struct OwnStream {
+  gp_ctx* ctx;
+  hipStream_t user = nullptr;
+  bool on = false;
+  int enter(gp_ctx* c) {
+    ctx = c;
+    user = c->stream;
+    if (!c->gstream) {
+      HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+      for (auto& e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(c->gev[0], user));
+    HIPCHK(hipStreamWaitEvent(c->gstream, c->gev[0], 0));
+    c->stream = c->gstream;
+    on = true;
+    return GP_OK;
+  }
+  ~OwnStream() {
+    if (!on) return;
+    (void)hipEventRecord(ctx->gev[1], ctx->gstream);
+    (void)hipStreamWaitEvent(user, ctx->gev[1], 0);
+    ctx->stream = user;
+  }
+};
+
 int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
              SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
   const int prec = cfg.precision;
+  OwnStream own;
+  if (cfg.use_graph) CHK(own.enter(ctx));
   Precond pcs;
   const Precond* pc = nullptr;
   if (cfg.precond_rank > 0) {
@@ -558,6 +593,39 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
   double last_true = std::numeric_limits<double>::infinity();
   int st = 0;
   Progress prog;
+  auto cg_iteration = [&]() -> int {
+    CHK(kprod(ctx, px, px, s.Dv, s.c, s.c, s.HD, s.c, prec, a2, s.Dv, s.c, s2));
+    {
+      ProfScope ps(ctx, 3);
+      HIPCHK(col_dot_partial(s.Dv, s.HD, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+      HIPCHK(cg_alpha(s.partial, s.nb, s.c, s.gamma, s.alpha, s.status, ctx->stream));
+      HIPCHK(cg_update_ur(s.Ut, s.R, s.Dv, s.HD, s.alpha, s.n, s.c, s.c, s.partial, s.nb,
+                          ctx->stream));
+      if (!pc) {
+        HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, s.rnorm, s.status, ctx->stream));
+        HIPCHK(cg_update_d(s.Dv, s.R, s.beta, s.n, s.c, s.c, ctx->stream));
+      }
+    }
+    if (pc) {
+      // p = P(r); beta = r.p / gamma; gamma = r.p; d = p + beta d
+      HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, nullptr, s.rnorm, s.status, ctx->stream));
+      CHK(pc_apply_cols(ctx, *pc, s.R, s.c, s.c, s.Z, s.c));
+      ProfScope ps(ctx, 3);
+      HIPCHK(col_dot_partial(s.R, s.Z, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
+      HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, nullptr, s.status, ctx->stream));
+      HIPCHK(cg_update_d(s.Dv, s.Z, s.beta, s.n, s.c, s.c, ctx->stream));
+    }
+    return GP_OK;
+  };
+  const bool use_graph = cfg.use_graph != 0;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_epoch = 0;
+  struct ExecGuard {
+    hipGraphExec_t* e;
+    ~ExecGuard() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+    }
+  } exec_guard{&graph_exec};
   while (true) {
     if (since_true == 0 || t % check == 0 || t >= cap) {
       CHK(read_norms(ctx, s, &ry, &rz, &st));
@@ -602,28 +670,34 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
       }
     }
     // One CG iteration (Algorithm 1), columns in parallel.
-    CHK(kprod(ctx, px, px, s.Dv, s.c, s.c, s.HD, s.c, prec, a2, s.Dv, s.c, s2));
+    if (graph_exec && ctx->alloc_epoch != graph_epoch) {
+      // a workspace moved since the capture: the graph's pointers are stale
+      HIPCHK(hipGraphExecDestroy(graph_exec));
+      graph_exec = nullptr;
+    }
+    if (graph_exec) {
+      HIPCHK(hipGraphLaunch(graph_exec, ctx->stream));
+    } else if (use_graph && t >= 1) {
+      // the first iteration ran eagerly, so every workspace has its final size:
+      // capture the second one (no allocation, synchronisation or memset inside)
+      const bool prof = ctx->prof;
+      ctx->prof = false;
+      HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+      const int rc = cg_iteration();
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+      ctx->prof = prof;
+      CHK(rc);
+      HIPCHK(ec);
+      const hipError_t ei = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(ei);
+      graph_epoch = ctx->alloc_epoch;
+      HIPCHK(hipGraphLaunch(graph_exec, ctx->stream));
+    } else {
+      CHK(cg_iteration());
+    }
     stats.matvecs += 1;
-    {
-      ProfScope ps(ctx, 3);
-      HIPCHK(col_dot_partial(s.Dv, s.HD, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
-      HIPCHK(cg_alpha(s.partial, s.nb, s.c, s.gamma, s.alpha, s.status, ctx->stream));
-      HIPCHK(cg_update_ur(s.Ut, s.R, s.Dv, s.HD, s.alpha, s.n, s.c, s.c, s.partial, s.nb,
-                          ctx->stream));
-      if (!pc) {
-        HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, s.rnorm, s.status, ctx->stream));
-        HIPCHK(cg_update_d(s.Dv, s.R, s.beta, s.n, s.c, s.c, ctx->stream));
-      }
-    }
-    if (pc) {
-      // p = P(r); beta = r.p / gamma; gamma = r.p; d = p + beta d
-      HIPCHK(gamma_from_partial(s.partial, s.nb, s.c, nullptr, s.rnorm, s.status, ctx->stream));
-      CHK(pc_apply_cols(ctx, *pc, s.R, s.c, s.c, s.Z, s.c));
-      ProfScope ps(ctx, 3);
-      HIPCHK(col_dot_partial(s.R, s.Z, s.n, s.c, s.c, s.c, s.partial, s.nb, ctx->stream));
-      HIPCHK(cg_beta(s.partial, s.nb, s.c, s.gamma, s.beta, nullptr, s.status, ctx->stream));
-      HIPCHK(cg_update_d(s.Dv, s.Z, s.beta, s.n, s.c, s.c, ctx->stream));
-    }
     ++t;
     ++since_true;
     if (mixed && cfg.refine_every > 0 && since_true >= cfg.refine_every) {
@@ -844,6 +918,12 @@ void gp_ctx_destroy(gp_ctx* ctx) {
       (void)hipEventDestroy(p.second);
     }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->gstream) {
+    (void)hipStreamSynchronize(ctx->gstream);
+    (void)hipStreamDestroy(ctx->gstream);
+  }
+  for (auto e : ctx->gev)
+    if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < B_COUNT; ++i)
     if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
@@ -1032,6 +1112,7 @@ void gp_solver_cfg_default(gp_solver_cfg* cfg) {
   cfg->sgd_batches_count = 0;
   cfg->sgd_seed = 0;
   cfg->precond_rank = 0;
+  cfg->use_graph = 0;
 }
 
 int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, const float* B,
