@@ -349,25 +349,32 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
 }
 
 // ---------------------------------------------------------------------------
-// Cross-term path (bf16 modes, d <= 3).  Points are packed as
-// [x^_0, x^_1, x^_2, |x^|^2]; with A'[j] = [-2 x^_j, |x^_j|^2] and
-// B'[i] = [x^_i, 1] one v_mfma_f32_16x16x4_f32 gives |x^_j|^2 - 2 x^_i.x^_j for a
-// 16 x 16 block and r^2 = that + |x^_i|^2, i.e. 2 VALU ops per kernel entry
-// instead of 2d on the direct path, and one scalar column load per lane and
-// half-step instead of eight points.  The product's output layout gives each
-// lane rows j = 4g..4g+3 (and 16 + 4g..) of one column i, so the V tiles are
-// packed with the matching row permutation (xt_k_of_j in vec.hip).  The FP32
-// cancellation error in r^2 grows with |x^|^2; the library uses this path only
-// when max |x^|^2 <= kXTMaxNorm2 and otherwise the direct path.
-template <int MODE>
-__device__ __forceinline__ void tile_a_xt(float bx, float ni, float ajl, float ajh, bf16x8& ah,
-                                          bf16x8& al) {
+// Cross-term path (bf16 modes, any d with every scaled point's |x^|^2 bounded).
+// Points are packed chunk-major, xt[q][i][0..3] for q < NK = ceil((d+1)/4):
+// coordinates in slots 0..d-1, |x^|^2 in the last slot 4NK-1, zeros between.
+// With A'[j] = [-2 x^_j, |x^_j|^2] and B'[i] = [x^_i, 1], NK chained
+// v_mfma_f32_16x16x4_f32 with |x^_i|^2 as the accumulator input give r^2 for a
+// 16 x 16 block, so the VALU only evaluates the Matern function and splits it,
+// each lane loads NK scalars per 16 columns (coalesced: lanes of a chunk read 64
+// consecutive floats), and no coordinates are held in registers beyond the NK
+// operands of the lane's rows.  The product's output layout gives each lane rows
+// j = 4g..4g+3 (and 16 + 4g..) of one column i, so the V tiles are packed with the
+// matching row permutation (xt_k_of_j in vec.hip).  The FP32 cancellation error
+// in r^2 grows with |x^|^2; the library uses this path only when
+// max |x^|^2 <= kXTMaxNorm2 and otherwise the direct path.
+template <int MODE, int NK>
+__device__ __forceinline__ void tile_a_xt(const float (&bx)[NK], float ni, const float (&ajl)[NK],
+                                          const float (&ajh)[NK], bf16x8& ah, bf16x8& al) {
   // |x^_i|^2 enters as the accumulator input; a slightly negative r^2 left by
   // cancellation is taken by magnitude (a free source modifier), which perturbs
   // m by the same O(|r^2 error|) as clamping at zero would
-  const f32x4 c = {ni, ni, ni, ni};
-  const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajl, bx, c, 0, 0, 0);
-  const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajh, bx, c, 0, 0, 0);
+  f32x4 d0 = {ni, ni, ni, ni};
+  f32x4 d1 = d0;
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajl[q], bx[q], d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajh[q], bx[q], d1, 0, 0, 0);
+  }
   float r2[8];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -392,51 +399,74 @@ __device__ __forceinline__ void tile_a_xt(float bx, float ni, float ajl, float a
   }
 }
 
-// One column step of the cross-term pipeline.  bh/bl hold the V tiles of step k;
-// the tiles of step k+1 are loaded into nbh/nbl at the start of the step, so their
-// latency is covered by a whole step of work.
-template <int MODE, int CT, int RS>
-__device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS], const float (&ni)[RS],
-                                             float ajl, float ajh, float& njl, float& njh,
-                                             const bf16x8 (&bh)[CT], const bf16x8 (&bl)[CT],
-                                             bf16x8 (&nbh)[CT], bf16x8 (&nbl)[CT],
+// A' operand of column rows j (lane's j = l%16 of each half) for the NK chunks,
+// scaled by -2 except in the norm slot.
+template <int NK>
+__device__ __forceinline__ void load_cols_xt(const float* __restrict__ xb, int64_t cstride,
+                                             int g, float (&jl)[NK], float (&jh)[NK]) {
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    const float mult = (q == NK - 1 && g == 3) ? 1.f : -2.f;
+    jl[q] = xb[q * cstride] * mult;
+    jh[q] = xb[q * cstride + 16 * 4] * mult;
+  }
+}
+
+template <int MODE, int CT, int RS, int NK>
+__device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS][NK], const float (&ni)[RS],
+                                             const float (&ajl)[NK], const float (&ajh)[NK],
+                                             float (&njl)[NK], float (&njh)[NK],
+                                             bf16x8 (&bh)[CT], bf16x8 (&bl)[CT],
                                              const bf16x8& a0h, const bf16x8& a0l, bf16x8& n0h,
                                              bf16x8& n0l, f32x4 (&acc)[RS][CT],
-                                             const float* __restrict__ xnext, float mult,
-                                             const uint16_t* __restrict__ vh_next,
+                                             const float* __restrict__ xnext, int64_t cstride,
+                                             int g, const uint16_t* __restrict__ vh_next,
                                              const uint16_t* __restrict__ vl_next) {
   constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    nbh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
-    if (MODE == P_BF16X3) nbl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
-  }
-  const float rl = xnext[0];
-  const float rh = xnext[16 * 4];
+  float rl[NK], rh[NK];
+  load_cols_xt<NK>(xnext, cstride, g, rl, rh);
   bf16x8 ah = a0h, al = a0l;
 #pragma unroll
   for (int r = 0; r + 1 < RS; ++r) {
     bf16x8 nh, nl;
-    tile_a_xt<MODE>(bx[r + 1], ni[r + 1], ajl, ajh, nh, nl);
+    tile_a_xt<MODE, NK>(bx[r + 1], ni[r + 1], ajl, ajh, nh, nl);
     mfma_tiles<MODE, CT>(acc[r], ah, al, bh, bl);
-    if (r == 0)
-      __builtin_amdgcn_sched_group_barrier(kMaskVMEMRead, (MODE == P_BF16X3 ? 2 : 1) * CT + 2, 0);
-    interleave<NM + 2, 4>();
+    interleave<NM + 2 * NK, 4>();
     __builtin_amdgcn_sched_barrier(0);
     ah = nh;
     al = nl;
   }
-  njl = rl * mult;
-  njh = rh * mult;
-  tile_a_xt<MODE>(bx[0], ni[0], njl, njh, n0h, n0l);
-  mfma_tiles<MODE, CT>(acc[RS - 1], ah, al, bh, bl);
-  interleave<NM + 2, 4>();
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    njl[q] = rl[q];
+    njh[q] = rh[q];
+  }
+  tile_a_xt<MODE, NK>(bx[0], ni[0], njl, njh, n0h, n0l);
+  if (MODE == P_BF16X3) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[RS - 1][ct], 0, 0, 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[RS - 1][ct], 0, 0, 0);
+      bl[ct] = *reinterpret_cast<const bf16x8*>(vl_next + ct * 512);
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    acc[RS - 1][ct] =
+        __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[RS - 1][ct], 0, 0, 0);
+    bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
+  }
+  interleave<NM + 2 * NK, 4>();
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int MODE, int CT, int RS>
+template <int MODE, int CT, int RS, int NK>
 __global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
-    const float* __restrict__ xp1, const float* __restrict__ xp2,
+    const float* __restrict__ xt1, const float* __restrict__ xt2, int64_t n2_pad,
     const uint16_t* __restrict__ vhi, const uint16_t* __restrict__ vlo, int64_t n1,
     int64_t n1_pad, int64_t steps, int S, float* __restrict__ out, int64_t ldo, int c,
     float* __restrict__ part, float scale, const float* __restrict__ vn, int64_t ldv,
@@ -450,16 +480,18 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
   const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
   const int64_t s0 = steps * sp / S;
   const int64_t s1 = steps * (sp + 1) / S;
+  const int64_t rstride = n1_pad * 4;  // floats per chunk of the row points
+  const int64_t cstride = n2_pad * 4;  // floats per chunk of the column points
 
-  // B' operand (k = g) and |x^_i|^2 of this lane's row in every sub-tile
-  float bx[RS], ni[RS];
+  // B' operand (k = g of every chunk) and |x^_i|^2 of this lane's row in every sub-tile
+  float bx[RS][NK], ni[RS];
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) {
-    const float* pi = xp1 + (row0 + rs * 16 + l16) * 4;
-    bx[rs] = g == 3 ? 1.f : pi[g];
-    ni[rs] = pi[3];
+    const float* pi = xt1 + (row0 + rs * 16 + l16) * 4;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) bx[rs][q] = (q == NK - 1 && g == 3) ? 1.f : pi[q * rstride + g];
+    ni[rs] = pi[(NK - 1) * rstride + 3];
   }
-  const float mult = g == 3 ? 1.f : -2.f;  // A'[j][g] = mult * packed[j][g]
 
   __shared__ float tot_lds[4][RS * CT * 4 * 64];
   float* tl = tot_lds[wave];
@@ -468,37 +500,36 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16_xt(
   zero<CT, RS>(acc);
 
   if (s0 < s1) {
-    const float* xb = xp2 + l16 * 4 + g;  // column j = 32 st + l16 (+16), coordinate g
+    const float* xb = xt2 + l16 * 4 + g;  // column j = 32 st + l16 (+16), slot g of each chunk
     const int64_t voff = l16 * 32 + 8 * g;
     const int64_t tstride = (int64_t)CT * 512;
-    float J0l, J0h, J1l, J1h;
-    bf16x8 B0h[CT], B0l[CT], B1h[CT], B1l[CT];
+    float J0l[NK], J0h[NK], J1l[NK], J1h[NK];
+    bf16x8 bh[CT], bl[CT];
     bf16x8 A0h, A0l, A1h, A1l;
-    J0l = xb[s0 * kJStep * 4] * mult;
-    J0h = xb[(s0 * kJStep + 16) * 4] * mult;
+    load_cols_xt<NK>(xb + s0 * kJStep * 4, cstride, g, J0l, J0h);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      B0h[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
+      bh[ct] = *reinterpret_cast<const bf16x8*>(vhi + s0 * tstride + voff + ct * 512);
       if (MODE == P_BF16X3)
-        B0l[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
+        bl[ct] = *reinterpret_cast<const bf16x8*>(vlo + s0 * tstride + voff + ct * 512);
     }
-    tile_a_xt<MODE>(bx[0], ni[0], J0l, J0h, A0h, A0l);
+    tile_a_xt<MODE, NK>(bx[0], ni[0], J0l, J0h, A0h, A0l);
     int64_t st = s0;
     int left = kChunk;
     while (true) {
       int64_t nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step_xt<MODE, CT, RS>(bx, ni, J0l, J0h, J1l, J1h, B0h, B0l, B1h, B1l, A0h, A0l, A1h,
-                                 A1l, acc, xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
-                                 vlo + nx * tstride + voff);
+      bf16_step_xt<MODE, CT, RS, NK>(bx, ni, J0l, J0h, J1l, J1h, bh, bl, A0h, A0l, A1h, A1l, acc,
+                                     xb + nx * kJStep * 4, cstride, g, vhi + nx * tstride + voff,
+                                     vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
         fold<CT, RS>(tl, acc, lane);
         left = kChunk;
       }
       nx = st + 1 < s1 ? st + 1 : st;
-      bf16_step_xt<MODE, CT, RS>(bx, ni, J1l, J1h, J0l, J0h, B1h, B1l, B0h, B0l, A1h, A1l, A0h,
-                                 A0l, acc, xb + nx * kJStep * 4, mult, vhi + nx * tstride + voff,
-                                 vlo + nx * tstride + voff);
+      bf16_step_xt<MODE, CT, RS, NK>(bx, ni, J1l, J1h, J0l, J0h, bh, bl, A1h, A1l, A0h, A0l, acc,
+                                     xb + nx * kJStep * 4, cstride, g, vhi + nx * tstride + voff,
+                                     vlo + nx * tstride + voff);
       if (++st >= s1) break;
       if (--left == 0) {
         fold<CT, RS>(tl, acc, lane);
@@ -643,23 +674,26 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
 
 template <int D, int CT>
 hipError_t launch(const FwdArgs& a, hipStream_t st) {
+  if (a.xt && a.prec != P_FP32) {
+    constexpr int NK = xt_chunks(D);
+    constexpr int RX = fwd_xt_row_subtiles(CT, NK);
+    if (a.n1_pad % (64 * RX) || !a.xt1 || !a.xt2) return hipErrorInvalidValue;
+    const dim3 gx((unsigned)(a.n1_pad / (64 * RX) * a.S));
+    if (a.prec == P_BF16X3)
+      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16X3, CT, RX, NK>), gx, dim3(256), 0, st, a.xt1, a.xt2,
+                         a.n2_pad, (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1,
+                         a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn,
+                         a.ldv, a.noise);
+    else
+      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16, CT, RX, NK>), gx, dim3(256), 0, st, a.xt1, a.xt2,
+                         a.n2_pad, (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1,
+                         a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn,
+                         a.ldv, a.noise);
+    return hipGetLastError();
+  }
   constexpr int RS = fwd_row_subtiles(CT);
   if (a.n1_pad % (64 * RS)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(a.n1_pad / (64 * RS) * a.S));
-  if constexpr (D <= 3) {
-    if (a.xt && a.prec == P_BF16X3) {
-      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16X3, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
-                         (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad,
-                         a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
-      return hipGetLastError();
-    }
-    if (a.xt && a.prec == P_BF16) {
-      hipLaunchKernelGGL((kfwd_bf16_xt<P_BF16, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
-                         (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1, a.n1_pad,
-                         a.steps, a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
-      return hipGetLastError();
-    }
-  }
   if (a.prec == P_BF16X3) {
     hipLaunchKernelGGL((kfwd_bf16<P_BF16X3, D, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const uint16_t*)a.vhi, (const uint16_t*)a.vlo, a.n1, a.n1_pad, a.steps,

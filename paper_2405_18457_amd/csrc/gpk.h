@@ -27,6 +27,10 @@ constexpr int kAdjRowsPerWG = 128;
 // Row sub-tiles of 16 rows per wave in the forward kernel (4 waves per
 // workgroup): 4 for up to 5 column tiles (80 columns), 2 for wider products.
 constexpr int fwd_row_subtiles(int CT) { return CT <= 5 ? 4 : 2; }
+// Cross-term path: K chunks of 4 (d coordinates + the squared norm) and row
+// sub-tiles per wave (fewer when many chunk operands occupy registers).
+constexpr int xt_chunks(int d) { return (d + 1 + 3) / 4; }
+constexpr int fwd_xt_row_subtiles(int CT, int NK) { return (CT <= 5 && NK <= 3) ? 4 : 2; }
 inline int fwd_rows_per_wg(int CT) { return 64 * fwd_row_subtiles(CT); }
 constexpr int kMaxD = 64;
 constexpr int kMaxC = 256;
@@ -55,8 +59,9 @@ hipError_t pack_x(const float* X, int64_t n, int d, int DP, const DimScale& sc, 
 hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, int DP,
                        const DimScale& sc, float* Xp, int64_t n_pad, hipStream_t st);
 // d <= 3: rows [x^_0, x^_1, x^_2, |x^|^2]; atomically records max |x^|^2 (float bits).
+// Cross-term layout with nk chunks (nk >= xt_chunks(d)); max |x^|^2 into maxbits.
 hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, const DimScale& sc,
-                      float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st);
+                      int nk, float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st);
 // Largest |x^|^2 for which the cross-term path is used: its FP32 cancellation
 // error in r^2 then stays near 1e-4 absolute (about 1e-5 relative in a product).
 constexpr float kXTMaxNorm2 = 1024.f;
@@ -95,7 +100,10 @@ struct FwdArgs {
   const float* vn = nullptr;       // [n1, ldv] or null
   int64_t ldv = 0;
   float noise = 0.f;
-  int xt = 0;                      // bf16 modes, D <= 3: distances from the MFMA cross term
+  int xt = 0;                      // cross-term path (bf16 modes)
+  const float* xt1 = nullptr;      // [xt_chunks(d)][n1_pad][4] row points (cross-term layout)
+  const float* xt2 = nullptr;      // [xt_chunks(d)][n2_pad][4] column points
+  int64_t n2_pad = 0;              // rows of xt2 per chunk
 };
 hipError_t fwd(const FwdArgs& a, hipStream_t st);
 // Sum of the S partial products plus the epilogue (used when S > 1).

@@ -26,7 +26,7 @@ enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
-  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_COUNT
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -34,10 +34,11 @@ constexpr int64_t kSafetyCap = 100000;
 constexpr int kProfClasses = 6;
 
 struct Packed {
-  float* xp = nullptr;
+  float* xp = nullptr;  // [n_pad, DP] scaled points
+  float* xt = nullptr;  // cross-term layout [xt_chunks(d)][n_pad][4] (== xp for d <= 3)
   int64_t n = 0, n_pad = 0;
   int D = 0, DP = 0;
-  bool xt_ok = false;  // |x^|^2 stored in slot 3 and small enough for the cross-term path
+  bool xt_ok = false;  // max |x^|^2 small enough for the cross-term path
 };
 
 }  // namespace
@@ -216,26 +217,31 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
   for (int k = 0; k < d; ++k) sc.s[k] = (float)(kSqrt3Log2e / theta[k]);
   CHK(ensure(ctx, id, (size_t)(p->n_pad * p->DP), &p->xp));
   p->xt_ok = false;
-  if (p->D <= 3) {
-    // squared norms ride in the padding slot; their maximum decides whether the
-    // cross-term distance form is accurate enough for these points
-    unsigned* mx;
-    CHK(ensure(ctx, B_XTMAX, 1, &mx));
-    CHK(ensure_pinned(ctx, 1));
-    HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), ctx->stream));
-    HIPCHK(pack_x_aug(X, idx, n, d, sc, p->xp, p->n_pad, mx, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->hpin, mx, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    unsigned bits;
-    std::memcpy(&bits, ctx->hpin, sizeof(unsigned));
-    float m;
-    std::memcpy(&m, &bits, sizeof(float));
-    p->xt_ok = std::isfinite(m) && m <= kXTMaxNorm2;
-  } else if (idx) {
-    HIPCHK(pack_x_rows(X, idx, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+  if (p->D > 3) {
+    if (idx)
+      HIPCHK(pack_x_rows(X, idx, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+    else
+      HIPCHK(pack_x(X, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+    CHK(ensure(ctx, id == B_XP1 ? B_XT1 : B_XT2, (size_t)(p->n_pad * 4 * xt_chunks(p->D)),
+               &p->xt));
   } else {
-    HIPCHK(pack_x(X, n, d, p->DP, sc, p->xp, p->n_pad, ctx->stream));
+    p->xt = p->xp;  // the cross-term layout is the packed layout (DP = 4, norm in slot 3)
   }
+  // squared norms ride in the last slot of the cross-term layout; their maximum
+  // decides whether the cross-term distance form is accurate enough for these points
+  unsigned* mx;
+  CHK(ensure(ctx, B_XTMAX, 1, &mx));
+  CHK(ensure_pinned(ctx, 1));
+  HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), ctx->stream));
+  // chunks for the kernel's dimension tier D (>= d), so kernel and layout agree
+  HIPCHK(pack_x_aug(X, idx, n, d, sc, xt_chunks(p->D), p->xt, p->n_pad, mx, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->hpin, mx, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  unsigned bits;
+  std::memcpy(&bits, ctx->hpin, sizeof(unsigned));
+  float m;
+  std::memcpy(&m, &bits, sizeof(float));
+  p->xt_ok = std::isfinite(m) && m <= kXTMaxNorm2;
   return GP_OK;
 }
 
@@ -270,6 +276,9 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     a.ldv = ldvn;
     a.noise = noise;
     a.xt = prec != GP_FP32 && fn == FN_MATERN && p1.xt_ok && p2.xt_ok;
+    a.xt1 = p1.xt;
+    a.xt2 = p2.xt;
+    a.n2_pad = p2.n_pad;
     const size_t vcount = (size_t)(p2.n_pad * 16 * CT);
     if (prec == GP_FP32) {
       float* vf;
@@ -285,7 +294,8 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
       a.vhi = hi;
       a.vlo = lo;
     }
-    const int64_t rowblocks = p1.n_pad / fwd_rows_per_wg(CT);
+    const int64_t rowblocks =
+        p1.n_pad / (64 * (a.xt ? fwd_xt_row_subtiles(CT, xt_chunks(p1.D)) : fwd_row_subtiles(CT)));
     a.S = choose_splits(rowblocks, a.steps);
     if (a.S > 1) CHK(ensure(ctx, B_PART, (size_t)(a.S * p1.n_pad * 16 * CT), &a.part));
     {

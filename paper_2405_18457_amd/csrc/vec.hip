@@ -36,18 +36,31 @@ __global__ void kpack_x(const float* __restrict__ X, const int32_t* __restrict__
 
 // Points with d <= 3 packed as [x^_0, x^_1, x^_2, |x^|^2] (unused coordinates 0);
 // the largest |x^|^2 is recorded (float bits, non-negative) for the caller.
+// Cross-term layout, chunk-major: Xp[(q * n_pad + i) * 4 + g] holds slot 4q + g of
+// point i: scaled coordinates in slots 0..d-1, |x^|^2 in the last slot 4nk-1,
+// zeros elsewhere and on padding rows.  The maximum |x^|^2 goes to maxbits.
 __global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restrict__ idx,
-                            int64_t n, int d, DimScale sc, float4* __restrict__ Xp,
+                            int64_t n, int d, DimScale sc, int nk, float* __restrict__ Xp,
                             int64_t n_pad, unsigned* __restrict__ maxbits) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n_pad) return;
-  float v[3] = {0.f, 0.f, 0.f};
-  if (i < n) {
-    const int64_t src = idx ? (int64_t)idx[i] : i;
-    for (int k = 0; k < d; ++k) v[k] = X[src * d + k] * sc.s[k];
+  const int64_t src = i < n ? (idx ? (int64_t)idx[i] : i) : 0;
+  float nn = 0.f;
+  if (i < n)
+    for (int k = 0; k < d; ++k) {
+      const float v = X[src * d + k] * sc.s[k];
+      nn = __builtin_fmaf(v, v, nn);
+    }
+  for (int q = 0; q < nk; ++q) {
+    float v[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int slot = 4 * q + g;
+      v[g] = (i < n && slot < d) ? X[src * d + slot] * sc.s[slot] : 0.f;
+      if (slot == 4 * nk - 1) v[g] = nn;
+    }
+    reinterpret_cast<float4*>(Xp)[q * n_pad + i] = make_float4(v[0], v[1], v[2], v[3]);
   }
-  const float nn = __builtin_fmaf(v[0], v[0], __builtin_fmaf(v[1], v[1], v[2] * v[2]));
-  Xp[i] = make_float4(v[0], v[1], v[2], nn);
   if (maxbits && i < n) atomicMax(maxbits, __builtin_bit_cast(unsigned, nn));
 }
 
@@ -404,9 +417,9 @@ hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, 
 }
 
 hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, const DimScale& sc,
-                      float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st) {
+                      int nk, float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st) {
   hipLaunchKernelGGL(kpack_x_aug, dim3(blocks_for(n_pad)), dim3(kThreads), 0, st, X, idx, n, d, sc,
-                     reinterpret_cast<float4*>(Xp), n_pad, maxbits);
+                     nk, Xp, n_pad, maxbits);
   return hipGetLastError();
 }
 
