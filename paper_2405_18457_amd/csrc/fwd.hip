@@ -672,8 +672,167 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
                    noise);
 }
 
+// FP32 cross-term kernel: r^2 as in kfwd_bf16_xt, then 8 K=4 FP32 MFMAs per
+// 16-column tile and step with the lane's 8 kernel values as scalar A operands
+// in the order the cross-term output leaves them (k = g of step kk holds column
+// j = 4g + kk for kk < 4 and 16 + 4g + kk - 4 after), so the FP32 V tiles are
+// packed with that row permutation.  Used under a tighter norm bound than the
+// bf16 modes (the FP32 product's own error is smaller).
+template <int NK>
+__device__ __forceinline__ void f32_tile_xt(const float (&bx)[NK], float ni, const float (&ajl)[NK],
+                                            const float (&ajh)[NK], float (&m)[8]) {
+  f32x4 d0 = {ni, ni, ni, ni};
+  f32x4 d1 = d0;
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajl[q], bx[q], d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ajh[q], bx[q], d1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    m[q] = matern_r2(__builtin_fabsf(d0[q]));
+    m[4 + q] = matern_r2(__builtin_fabsf(d1[q]));
+  }
+}
+
+template <int CT, int RS, int NK>
+__device__ __forceinline__ void f32_step_xt(const float (&bx)[RS][NK], const float (&ni)[RS],
+                                            const float (&ajl)[NK], const float (&ajh)[NK],
+                                            float (&njl)[NK], float (&njh)[NK], float (&b)[CT][8],
+                                            const float (&a0)[8], float (&n0)[8],
+                                            f32x4 (&acc)[RS][CT],
+                                            const float* __restrict__ xnext, int64_t cstride,
+                                            int g, const float* __restrict__ vnext) {
+  float rl[NK], rh[NK];
+  load_cols_xt<NK>(xnext, cstride, g, rl, rh);
+  float a[8];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) a[kk] = a0[kk];
+#pragma unroll
+  for (int r = 0; r + 1 < RS; ++r) {
+    float nx[8];
+    f32_tile_xt<NK>(bx[r + 1], ni[r + 1], ajl, ajh, nx);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[r][ct], 0, 0, 0);
+    interleave<8 * CT + 2 * NK, 2>();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = nx[kk];
+  }
+#pragma unroll
+  for (int q = 0; q < NK; ++q) {
+    njl[q] = rl[q];
+    njh[q] = rh[q];
+  }
+  f32_tile_xt<NK>(bx[0], ni[0], njl, njh, n0);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[RS - 1][ct], 0, 0, 0);
+    const float4 lo4 = *reinterpret_cast<const float4*>(vnext + ct * 512);
+    const float4 hi4 = *reinterpret_cast<const float4*>(vnext + ct * 512 + 4);
+    b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
+    b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
+  }
+  interleave<8 * CT + 2 * NK, 2>();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int CT, int RS, int NK>
+__global__ __launch_bounds__(256, 2) void kfwd_f32_xt(
+    const float* __restrict__ xt1, const float* __restrict__ xt2, int64_t n2_pad,
+    const float* __restrict__ vf, int64_t n1, int64_t n1_pad, int64_t steps, int S,
+    float* __restrict__ out, int64_t ldo, int c, float* __restrict__ part, float scale,
+    const float* __restrict__ vn, int64_t ldv, float noise) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int l16 = lane & 15;
+  const int g = lane >> 4;
+  const int64_t rb = blockIdx.x / S;
+  const int64_t sp = blockIdx.x % S;
+  const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
+  const int64_t s0 = steps * sp / S;
+  const int64_t s1 = steps * (sp + 1) / S;
+  const int64_t rstride = n1_pad * 4;
+  const int64_t cstride = n2_pad * 4;
+
+  float bx[RS][NK], ni[RS];
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) {
+    const float* pi = xt1 + (row0 + rs * 16 + l16) * 4;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) bx[rs][q] = (q == NK - 1 && g == 3) ? 1.f : pi[q * rstride + g];
+    ni[rs] = pi[(NK - 1) * rstride + 3];
+  }
+
+  __shared__ float tot_lds[4][RS * CT * 4 * 64];
+  float* tl = tot_lds[wave];
+  tot_init<CT, RS>(tl, lane);
+  f32x4 acc[RS][CT];
+  zero<CT, RS>(acc);
+
+  if (s0 < s1) {
+    const float* xb = xt2 + l16 * 4 + g;
+    const int64_t voff = (l16 * 4 + g) * 8;
+    const int64_t tstride = (int64_t)CT * 512;
+    float J0l[NK], J0h[NK], J1l[NK], J1h[NK];
+    float b[CT][8];
+    float A0[8], A1[8];
+    load_cols_xt<NK>(xb + s0 * kJStep * 4, cstride, g, J0l, J0h);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const float* p = vf + s0 * tstride + voff + ct * 512;
+      const float4 lo4 = *reinterpret_cast<const float4*>(p);
+      const float4 hi4 = *reinterpret_cast<const float4*>(p + 4);
+      b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
+      b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
+    }
+    f32_tile_xt<NK>(bx[0], ni[0], J0l, J0h, A0);
+    int64_t st = s0;
+    int left = kChunk;
+    while (true) {
+      int64_t nx = st + 1 < s1 ? st + 1 : st;
+      f32_step_xt<CT, RS, NK>(bx, ni, J0l, J0h, J1l, J1h, b, A0, A1, acc, xb + nx * kJStep * 4,
+                              cstride, g, vf + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT, RS>(tl, acc, lane);
+        left = kChunk;
+      }
+      nx = st + 1 < s1 ? st + 1 : st;
+      f32_step_xt<CT, RS, NK>(bx, ni, J1l, J1h, J0l, J0h, b, A1, A0, acc, xb + nx * kJStep * 4,
+                              cstride, g, vf + nx * tstride + voff);
+      if (++st >= s1) break;
+      if (--left == 0) {
+        fold<CT, RS>(tl, acc, lane);
+        left = kChunk;
+      }
+    }
+    fold<CT, RS>(tl, acc, lane);
+  }
+  f32x4 tot[RS][CT];
+  tot_read<CT, RS>(tl, tot, lane);
+  epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv,
+                   noise);
+}
+
 template <int D, int CT>
 hipError_t launch(const FwdArgs& a, hipStream_t st) {
+  if (a.xt && a.prec == P_FP32 && a.fn == FN_MATERN) {
+    constexpr int NK = xt_chunks(D);
+    constexpr int RX = fwd_xt_row_subtiles(CT, NK);
+    if (a.n1_pad % (64 * RX) || !a.xt1 || !a.xt2) return hipErrorInvalidValue;
+    const dim3 gx((unsigned)(a.n1_pad / (64 * RX) * a.S));
+    hipLaunchKernelGGL((kfwd_f32_xt<CT, RX, NK>), gx, dim3(256), 0, st, a.xt1, a.xt2, a.n2_pad,
+                       (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,
+                       a.part, a.scale, a.vn, a.ldv, a.noise);
+    return hipGetLastError();
+  }
   if (a.xt && a.prec != P_FP32) {
     constexpr int NK = xt_chunks(D);
     constexpr int RX = fwd_xt_row_subtiles(CT, NK);

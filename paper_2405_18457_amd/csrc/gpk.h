@@ -64,14 +64,15 @@ hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, cons
                       int nk, float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st);
 // Largest |x^|^2 for which the cross-term path is used: its FP32 cancellation
 // error in r^2 then stays near 1e-4 absolute (about 1e-5 relative in a product).
-constexpr float kXTMaxNorm2 = 1024.f;
+constexpr float kXTMaxNorm2 = 1024.f;     // bf16 modes
+constexpr float kXTMaxNorm2F32 = 400.f;   // FP32 mode (its own error budget is tighter)
 // V [n, ldv] (first c columns, optional per-column scale) into forward tiles;
 // perm = the row order of the cross-term path (see fwd.hip).
 hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
                        int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, bool perm,
                        hipStream_t st);
 hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
-                      int CT, float* out, int64_t n_pad, hipStream_t st);
+                      int CT, float* out, int64_t n_pad, bool perm, hipStream_t st);
 // Row-major [n_pad, 32*KT] packs for the adjoint (optional per-column weights).
 hipError_t pack_rows_bf16(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
                           int KT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st);

@@ -38,7 +38,8 @@ struct Packed {
   float* xt = nullptr;  // cross-term layout [xt_chunks(d)][n_pad][4] (== xp for d <= 3)
   int64_t n = 0, n_pad = 0;
   int D = 0, DP = 0;
-  bool xt_ok = false;  // max |x^|^2 small enough for the cross-term path
+  bool xt_ok = false;  // max |x^|^2 small enough for the cross-term path (bf16 modes)
+  bool xt_ok32 = false;  // ... and for the FP32 mode
 };
 
 }  // namespace
@@ -242,6 +243,7 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
   float m;
   std::memcpy(&m, &bits, sizeof(float));
   p->xt_ok = std::isfinite(m) && m <= kXTMaxNorm2;
+  p->xt_ok32 = std::isfinite(m) && m <= kXTMaxNorm2F32;
   return GP_OK;
 }
 
@@ -275,7 +277,8 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     a.vn = vn ? vn + c0 : nullptr;
     a.ldv = ldvn;
     a.noise = noise;
-    a.xt = prec != GP_FP32 && fn == FN_MATERN && p1.xt_ok && p2.xt_ok;
+    a.xt = fn == FN_MATERN && (prec == GP_FP32 ? (p1.xt_ok32 && p2.xt_ok32)
+                                               : (p1.xt_ok && p2.xt_ok));
     a.xt1 = p1.xt;
     a.xt2 = p2.xt;
     a.n2_pad = p2.n_pad;
@@ -283,7 +286,8 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     if (prec == GP_FP32) {
       float* vf;
       CHK(ensure(ctx, B_VHI, vcount, &vf));
-      HIPCHK(pack_v_f32(V + c0, p2.n, ldv, cs, nullptr, CT, vf, p2.n_pad, ctx->stream));
+      HIPCHK(pack_v_f32(V + c0, p2.n, ldv, cs, nullptr, CT, vf, p2.n_pad, a.xt != 0,
+                        ctx->stream));
       a.vhi = vf;
     } else {
       uint16_t *hi, *lo = nullptr;

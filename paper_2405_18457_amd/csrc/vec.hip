@@ -91,7 +91,7 @@ __global__ void kpack_v_bf16(const float* __restrict__ V, int64_t n, int64_t ldv
 
 __global__ void kpack_v_f32(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
                             const float* __restrict__ colscale, int CT, float* __restrict__ out,
-                            int64_t n_pad) {
+                            int64_t n_pad, int perm) {
   const int CP = 16 * CT;
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t >= n_pad * CP) return;
@@ -100,7 +100,11 @@ __global__ void kpack_v_f32(const float* __restrict__ V, int64_t n, int64_t ldv,
   float v = 0.f;
   if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
   const int jj = (int)(j % 32);
-  const int64_t off = ((j / 32) * CT + col / 16) * 512 + ((col % 16) * 4 + (jj % 4)) * 8 + jj / 4;
+  // lane group g and MFMA step kk that consume row jj of the 32-row tile: row
+  // g + 4 kk (direct kernel) or the cross-term output order (see fwd.hip)
+  const int g = perm ? (jj & 15) >> 2 : jj % 4;
+  const int kk = perm ? (jj & 3) + 4 * (jj >> 4) : jj / 4;
+  const int64_t off = ((j / 32) * CT + col / 16) * 512 + ((col % 16) * 4 + g) * 8 + kk;
   out[off] = v;
 }
 
@@ -432,9 +436,9 @@ hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const floa
 }
 
 hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
-                      int CT, float* out, int64_t n_pad, hipStream_t st) {
+                      int CT, float* out, int64_t n_pad, bool perm, hipStream_t st) {
   hipLaunchKernelGGL(kpack_v_f32, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V, n,
-                     ldv, c, colscale, CT, out, n_pad);
+                     ldv, c, colscale, CT, out, n_pad, (int)perm);
   return hipGetLastError();
 }
 
