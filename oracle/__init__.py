@@ -24,12 +24,15 @@ Processes", NeurIPS 2024) in float64, slow and obvious:
   precond  -- the rank-k pivoted Cholesky preconditioner of CG (App. B).
   optim    -- softplus / log reparameterisation and Adam (App. B "Iterative
               Optimiser").
+  init_heuristic -- initial hyperparameters of the large data sets: nearest
+              subsets around random centroids, exact-likelihood maximisation,
+              centroid average (App. B "Iterative Optimiser").
 
 Parity status: every function has at least one independent pin in
 ``tests/test_oracle_pins.py`` except the alternating-projections block
 *selection order* (any argmax rule gives a valid AP; the paper's code is not
 available), which is marked "parity unpinned" in ``solvers.ap``.
 """
-from . import kernel, mll, rff, solvers, optim, train, precond  # noqa: F401
+from . import kernel, mll, rff, solvers, optim, train, precond, init_heuristic  # noqa: F401
 
-__all__ = ["kernel", "mll", "rff", "solvers", "optim", "train", "precond"]
+__all__ = ["kernel", "mll", "rff", "solvers", "optim", "train", "precond", "init_heuristic"]

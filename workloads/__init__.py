@@ -12,6 +12,7 @@ cfg = 0..4 for the five workloads below and these stream numbers:
   3 truth RFF weights   4 observation noise      5 model probes Z / model RFF frequencies
   6 model RFF weights   7 noise base w_eps       8 SGD batch indices
   9 random hyperparameters (differentiation workload)
+ 10 centroid rows of the initial-hyperparameter heuristic
 
 All arrays handed to a device are float32 (inputs are *defined* as their
 float32 values; the oracle up-casts the very same numbers to float64).
@@ -34,7 +35,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "rng", "draw_inputs", "draw_true_lengthscales",
     "draw_spectral_t3", "draw_normal", "draw_batch_indices", "draw_random_theta",
-    "truth_draws", "model_pathwise_draws", "model_standard_probes",
+    "truth_draws", "model_pathwise_draws", "model_standard_probes", "draw_centroids",
 ]
 
 
@@ -158,3 +159,10 @@ def model_standard_probes(w: Workload, n: int | None = None, s: int | None = Non
     n = w.n if n is None else n
     s = w.s if s is None else s
     return draw_normal(rng(w.index, 5), (n, s))
+
+
+def draw_centroids(w: Workload, count: int = 10, n: int | None = None) -> np.ndarray:
+    """Centroid rows of the initial-hyperparameter heuristic: ``count`` indices drawn
+    uniformly from [0, n), independently (int64)."""
+    n = w.n if n is None else n
+    return rng(w.index, 10).integers(0, n, size=count, dtype=np.int64)
