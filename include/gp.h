@@ -6,7 +6,8 @@
  * the matrix-free regularised kernel block product (K + sigma^2 I) V behind
  * every solver iteration and gradient estimate, the three linear solvers of
  * its App. B (Algorithms 1-3), the standard and pathwise gradient estimators
- * (Secs. 2-3) and random-Fourier-feature prior samples (App. B).
+ * (Secs. 2-3), random-Fourier-feature prior samples (App. B) and the
+ * initial-hyperparameter heuristic of its large-data experiments (App. B).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -93,7 +94,8 @@ const char* gp_version(void);
  *   0 = forward product kernel in GP_BF16X3 / GP_BF16, 1 = fused adjoint,
  *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product kernel
  *   in GP_FP32 (classes 0 and 4 time the product kernel alone, not the sum of
- *   its column-split partials), 5 = CG preconditioner (construction and apply).
+ *   its column-split partials), 5 = CG preconditioner (construction and apply),
+ *   6 = initial-hyperparameter heuristic (nearest rows, exact likelihood).
  * Errors: GP_ERR_INVALID_ARG for an unknown class.                          */
 int gp_profile_enable(gp_ctx* ctx, int enable);
 int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);
@@ -267,6 +269,59 @@ int gp_adam_ascent(int p, double* nu, double* m, double* v, int64_t* step,
 
 /* theta[k] = softplus(nu[k]) or exp(nu[k]) (HOST arrays [p]). */
 int gp_nu_to_theta(int p, const double* nu, int transform, double* theta);
+
+/* ------------------------------------ initial hyperparameters (large data) */
+
+/* Step 2 of the initial-hyperparameter heuristic (App. B, "Iterative
+ * Optimiser"): the k rows of X nearest to row `centre`.  Distance: squared
+ * Euclidean distance in the raw inputs, summed in FP64 in dimension order with
+ * every product and sum rounded separately (no fused multiply-add); equal
+ * distances go to the lower row index.
+ *   X [n, d]; centre in [0, n) (drawn uniformly at random by the caller, step 1);
+ *   idx DEVICE [k] int64 output, the selected rows in ascending order.
+ * k = 0 is a no-op; k = n returns 0..n-1.
+ * Errors: GP_ERR_INVALID_ARG (k < 0, k > n, centre outside [0, n), NULL
+ * pointers, d outside [1, 64]), GP_ERR_HIP.                                 */
+int gp_nearest(gp_ctx* ctx, const float* X, int64_t n, int d, int64_t centre, int64_t k,
+               int64_t* idx);
+
+/* Exact log marginal likelihood and its gradient (Sec. 2, eqs. mll and
+ * mll_grad) on m rows of (X, y), by a dense FP64 Cholesky factorisation:
+ *   L   = -1/2 y^T H^-1 y - 1/2 log det H - m/2 log 2 pi
+ *   g_k = 1/2 alpha^T dH_k alpha - 1/2 tr(H^-1 dH_k),  alpha = H^-1 y.
+ * The rows are idx[0..m) (DEVICE int64, each in [0, n)) or, with idx = NULL,
+ * rows 0..m-1.  X [n, d], y [n] DEVICE.  mll: HOST double out (may be NULL);
+ * grad: HOST [d+2] doubles out (ell_1..ell_d, a, sigma; may be NULL).
+ * Workspace: two (m rounded up to 64)^2 FP64 matrices.
+ * Errors: GP_ERR_INVALID_ARG (m < 1, m > 32768, m > n without idx, an index
+ * outside [0, n), theta <= 0), GP_ERR_BREAKDOWN (a non-positive pivot: H is
+ * not numerically positive definite), GP_ERR_NO_WORKSPACE, GP_ERR_HIP.      */
+int gp_exact_mll(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                 const int64_t* idx, int64_t m, const double* theta, double* mll, double* grad);
+
+typedef struct gp_init_cfg {
+  int steps;             /* Adam steps per centroid subset (default 100)            */
+  double lr;             /* Adam learning rate (default 0.1)                        */
+  int transform;         /* GP_SOFTPLUS (default) or GP_LOG                         */
+  const double* theta0;  /* HOST [d+2] starting point; NULL = 1.0 for every entry   */
+} gp_init_cfg;
+
+/* Defaults: the paper's small-data optimiser settings (App. B: hyperparameters
+ * initialised at 1.0, learning rate 0.1, 100 Adam steps, softplus).          */
+void gp_init_cfg_default(gp_init_cfg* cfg);
+
+/* The initial-hyperparameter heuristic for large data sets (App. B,
+ * "Iterative Optimiser"): for every centroid row c in centres (HOST [nc],
+ * drawn uniformly by the caller), take the m rows nearest to it (gp_nearest),
+ * maximise the exact marginal likelihood on them with Adam (gp_exact_mll and
+ * gp_adam_ascent, cfg), and return the arithmetic mean of the resulting theta.
+ *   X [n, d], y [n] DEVICE; theta_out HOST [d+2]; theta_each HOST [nc, d+2]
+ *   (per-centroid results, may be NULL).  The paper uses m = 10,000, nc = 10.
+ * Errors: as gp_nearest and gp_exact_mll; GP_ERR_INVALID_ARG also for nc < 1,
+ * m > n, steps < 0, lr <= 0 or an invalid theta0.                            */
+int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                      const int64_t* centres, int nc, int64_t m, const gp_init_cfg* cfg,
+                      double* theta_out, double* theta_each);
 
 #ifdef __cplusplus
 }

@@ -28,7 +28,7 @@ EXPORTS = (
     "gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_profile_enable",
     "gp_profile_read", "gp_kmatvec", "gp_kmatvec_adjoint", "gp_solver_cfg_default", "gp_solve",
     "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_pivoted_cholesky",
-    "gp_posterior_sample",
+    "gp_posterior_sample", "gp_nearest", "gp_exact_mll", "gp_init_cfg_default", "gp_init_heuristic",
 )
 
 
@@ -53,6 +53,13 @@ class SolveStats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class InitCfg(C.Structure):
+    _fields_ = [
+        ("steps", C.c_int), ("lr", C.c_double), ("transform", C.c_int),
+        ("theta0", C.POINTER(C.c_double)),
+    ]
 
 
 _lib = None
@@ -92,6 +99,11 @@ def lib():
                                           C.POINTER(C.c_int)]),
             "gp_posterior_sample": (i32, [vp, vp, i64, vp, i64, i32, pd, vp, i32, vp, i64, vp,
                                           i64, i32, i32, vp, i64]),
+            "gp_nearest": (i32, [vp, vp, i64, i32, i64, i64, vp]),
+            "gp_exact_mll": (i32, [vp, vp, i64, i32, vp, vp, i64, pd, pd, pd]),
+            "gp_init_cfg_default": (None, [C.POINTER(InitCfg)]),
+            "gp_init_heuristic": (i32, [vp, vp, i64, i32, vp, pi64, i32, i64, C.POINTER(InitCfg),
+                                        pd, pd]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

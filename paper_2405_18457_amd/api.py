@@ -14,8 +14,8 @@ import torch
 
 from . import _native as N
 from ._native import (GP_ADJ_FUSED, GP_ADJ_PER_PARAM, GP_AP, GP_BF16, GP_BF16X3, GP_CG,  # noqa: F401
-                      GP_FP32, GP_LOG, GP_PATHWISE, GP_SGD, GP_SOFTPLUS, GP_STANDARD, SolveStats,
-                      SolverCfg)
+                      GP_FP32, GP_LOG, GP_PATHWISE, GP_SGD, GP_SOFTPLUS, GP_STANDARD, InitCfg,
+                      SolveStats, SolverCfg)
 
 
 class GPError(RuntimeError):
@@ -233,6 +233,70 @@ def gp_mll_grad(ctx: Context, X, y, theta, estimator, U, cfg: SolverCfg, Z=None,
                                   ldw, e, lde, u, ldu, C.byref(cfg), adjoint_mode,
                                   grad.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)))
     return grad, st.as_dict()
+
+
+def _xdev(X):
+    if not X.is_cuda or X.dtype != torch.float32 or X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous [n, d] float32 device tensor")
+    return X.shape[0], X.shape[1]
+
+
+def gp_nearest(ctx: Context, X, centre, k):
+    """The k rows of X nearest to row ``centre`` (ascending row order, int64 device tensor)."""
+    n, d = _xdev(X)
+    idx = torch.empty(max(int(k), 1), device=X.device, dtype=torch.int64)
+    ctx.check(N.lib().gp_nearest(ctx.handle, C.c_void_p(X.data_ptr()), n, d, int(centre), int(k),
+                                 C.c_void_p(idx.data_ptr())))
+    return idx[:int(k)]
+
+
+def gp_exact_mll(ctx: Context, X, y, theta, idx=None, m=None):
+    """Exact log marginal likelihood and gradient on rows idx of (X, y) (all rows, or the
+    first m, when idx is None): returns (mll, grad [d+2])."""
+    n, d = _xdev(X)
+    if y.dtype != torch.float32 or not y.is_cuda or not y.is_contiguous():
+        raise ValueError("y must be a contiguous float32 device tensor")
+    ip = None
+    if idx is not None:
+        if idx.dtype != torch.int64 or not idx.is_cuda or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 device tensor")
+        ip = C.c_void_p(idx.data_ptr())
+        m = idx.shape[0]
+    elif m is None:
+        m = n
+    th, thp = _theta(theta)
+    out = C.c_double(0.0)
+    grad = np.zeros(d + 2)
+    ctx.check(N.lib().gp_exact_mll(ctx.handle, C.c_void_p(X.data_ptr()), n, d,
+                                   C.c_void_p(y.data_ptr()), ip, int(m), thp, C.byref(out),
+                                   grad.ctypes.data_as(C.POINTER(C.c_double))))
+    return out.value, grad
+
+
+def gp_init_heuristic(ctx: Context, X, y, centres, m, steps=100, lr=0.1, transform=GP_SOFTPLUS,
+                      theta0=None):
+    """Initial hyperparameters from the exact likelihood on the m rows nearest to each
+    centroid row: returns (mean theta [d+2], per-centroid theta [nc, d+2])."""
+    n, d = _xdev(X)
+    if y.dtype != torch.float32 or not y.is_cuda or not y.is_contiguous():
+        raise ValueError("y must be a contiguous float32 device tensor")
+    cen = np.ascontiguousarray(np.asarray(centres, dtype=np.int64))
+    cfg = InitCfg()
+    N.lib().gp_init_cfg_default(C.byref(cfg))
+    cfg.steps, cfg.lr, cfg.transform = int(steps), float(lr), int(transform)
+    t0 = None
+    if theta0 is not None:
+        t0 = np.ascontiguousarray(np.asarray(theta0, dtype=np.float64))
+        cfg.theta0 = t0.ctypes.data_as(C.POINTER(C.c_double))
+    out = np.zeros(d + 2)
+    each = np.zeros((cen.size, d + 2))
+    pd = C.POINTER(C.c_double)
+    ctx.check(N.lib().gp_init_heuristic(ctx.handle, C.c_void_p(X.data_ptr()), n, d,
+                                        C.c_void_p(y.data_ptr()),
+                                        cen.ctypes.data_as(C.POINTER(C.c_int64)), cen.size, int(m),
+                                        C.byref(cfg), out.ctypes.data_as(pd),
+                                        each.ctypes.data_as(pd)))
+    return out, each
 
 
 def gp_nu_to_theta(nu, transform=GP_SOFTPLUS):

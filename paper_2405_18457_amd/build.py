@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libgpmi.so")
 ARCH = "gfx950"
 DIMS = (1, 2, 3, 4, 8, 12, 16, 24, 32, 64)
 PER_DIM = ("fwd", "adj", "rff")
-SINGLE = ("dispatch", "vec", "solve", "precond", "runtime")
+SINGLE = ("dispatch", "vec", "solve", "precond", "exact", "nearest", "runtime")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from emitting packed-FP32 VALU ops

@@ -275,4 +275,38 @@ hipError_t add_block(float* Y, int64_t ldy, int64_t base, int bk, const float* X
 hipError_t sgd_fix(float* G, int64_t ldg, const float* Ut, const float* Bt, int64_t ld,
                    const int32_t* idx, int64_t b, int c, float s2, hipStream_t st);
 
+// ---------------------------------------------- initial-hyperparameter heuristic
+// nearest.hip: the k rows of X nearest to row `centre` (squared Euclidean
+// distance in FP64, dimension order, no fused multiply-add; ties to the lower
+// row), written to idx in ascending row order.  key [n], cnt [2 nearest_blocks(n)]
+// and st are scratch.
+struct SelState {
+  uint64_t prefix;
+  uint64_t mask;
+  int64_t want;
+  unsigned hist[256];
+};
+int64_t nearest_blocks(int64_t n);
+hipError_t nearest(const float* X, int64_t n, int d, int64_t centre, int64_t k, uint64_t* key,
+                   SelState* st, int64_t* cnt, int64_t* idx, hipStream_t s);
+
+// exact.hip: dense FP64 exact marginal likelihood on m gathered rows, padded to
+// m_p (a multiple of kExactTile).  A, W: m_p x m_p scratch; xs [m_p, d], ys, diag,
+// v, alpha [m_p]; part [exact_part_doubles]; gpart [exact_gpart_doubles];
+// out [d + 4] = (y^T alpha, log det H, gradient (ell_1..ell_d, a, sigma)).
+// status bit 1: an index outside [0, n); bit 2: a non-positive pivot.
+constexpr int kExactTile = 64;
+constexpr int kExactChunk = 256;
+constexpr int64_t kExactMaxM = 32768;
+enum ExFlags { kExLowerC = 1, kExALower = 2, kExAUpper = 4, kExBLower = 8, kExBUpper = 16 };
+hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, int64_t m,
+                        int64_t mp, const float* y, double* xs, double* ys, int* status,
+                        hipStream_t st);
+hipError_t exact_eval(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
+                      const double* inv_ell, double a, double sigma, double* A, double* W,
+                      double* diag, double* v, double* alpha, double* part, double* gpart,
+                      double* out, int* status, hipStream_t st);
+int64_t exact_part_doubles(int64_t mp);
+int64_t exact_gpart_doubles(int64_t mp, int d);
+
 }  // namespace gpk

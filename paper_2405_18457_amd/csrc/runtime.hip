@@ -26,12 +26,14 @@ enum BufId {
   B_XP1, B_XP2, B_VHI, B_VLO, B_PART, B_BT, B_UT, B_R, B_DV, B_HD, B_AUX, B_MOM, B_SCALD,
   B_SCALF, B_PARTIAL, B_STATUS, B_UHI, B_ULO, B_WHI, B_WLO, B_ADJP, B_OMEGA, B_INVELL, B_RHS,
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
-  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2, B_COUNT
+  B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2,
+  B_EXA, B_EXW, B_EXXS, B_EXYS, B_EXDG, B_EXV, B_EXAL, B_EXPART, B_EXGP, B_EXOUT, B_EXIE, B_EXST,
+  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
 constexpr int64_t kSafetyCap = 100000;
-constexpr int kProfClasses = 6;
+constexpr int kProfClasses = 7;
 
 struct Packed {
   float* xp = nullptr;  // [n_pad, DP] scaled points
@@ -1396,3 +1398,196 @@ int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* 
 }
 
 }  // namespace
+
+// ------------------------------------------- initial-hyperparameter heuristic
+namespace {
+
+struct ExactWs {
+  double *A, *W, *xs, *ys, *diag, *v, *alpha, *part, *gpart, *out, *inv_ell;
+  int* status;
+  int64_t m, mp;
+  int d;
+};
+
+// Workspace and the gathered rows (FP64) of one exact-likelihood subset.
+int exact_prepare(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                  const int64_t* idx, int64_t m, ExactWs& ws) {
+  ws.m = m;
+  ws.d = d;
+  ws.mp = round_up(m, kExactTile);
+  const size_t mp = (size_t)ws.mp;
+  CHK(ensure(ctx, B_EXA, mp * mp, &ws.A));
+  CHK(ensure(ctx, B_EXW, mp * mp, &ws.W));
+  CHK(ensure(ctx, B_EXXS, mp * d, &ws.xs));
+  CHK(ensure(ctx, B_EXYS, mp, &ws.ys));
+  CHK(ensure(ctx, B_EXDG, mp, &ws.diag));
+  CHK(ensure(ctx, B_EXV, mp, &ws.v));
+  CHK(ensure(ctx, B_EXAL, mp, &ws.alpha));
+  CHK(ensure(ctx, B_EXPART, (size_t)exact_part_doubles(ws.mp), &ws.part));
+  CHK(ensure(ctx, B_EXGP, (size_t)exact_gpart_doubles(ws.mp, d), &ws.gpart));
+  CHK(ensure(ctx, B_EXOUT, (size_t)kMaxD + 4, &ws.out));
+  CHK(ensure(ctx, B_EXIE, (size_t)kMaxD, &ws.inv_ell));
+  CHK(ensure(ctx, B_EXST, 1, &ws.status));
+  HIPCHK(hipMemsetAsync(ws.status, 0, sizeof(int), ctx->stream));
+  HIPCHK(exact_gather(X, n, d, idx, m, ws.mp, y, ws.xs, ws.ys, ws.status, ctx->stream));
+  return GP_OK;
+}
+
+// L and dL/dtheta at theta on the prepared subset (synchronises the stream).
+int exact_run(gp_ctx* ctx, const ExactWs& ws, const double* theta, double* mll, double* grad) {
+  const int d = ws.d;
+  CHK(ensure_pinned(ctx, 2 * (size_t)kMaxD + 16));
+  double* hin = ctx->hpin;
+  double* hout = ctx->hpin + kMaxD;
+  for (int k = 0; k < d; ++k) hin[k] = 1.0 / theta[k];
+  HIPCHK(hipMemcpyAsync(ws.inv_ell, hin, d * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  {
+    ProfScope ps(ctx, 6);
+    HIPCHK(exact_eval(ws.xs, ws.ys, d, ws.m, ws.mp, ws.inv_ell, theta[d], theta[d + 1], ws.A, ws.W,
+                      ws.diag, ws.v, ws.alpha, ws.part, ws.gpart, ws.out, ws.status,
+                      ctx->stream));
+  }
+  HIPCHK(hipMemcpyAsync(hout, ws.out, (d + 4) * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  int* hst = reinterpret_cast<int*>(ctx->hpin + 2 * kMaxD + 8);
+  HIPCHK(hipMemcpyAsync(hst, ws.status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*hst & 1) return fail(ctx, GP_ERR_INVALID_ARG, "a row index lies outside [0, n)");
+  if (*hst & 2)
+    return fail(ctx, GP_ERR_BREAKDOWN,
+                "non-positive pivot in the Cholesky factorisation of H (m = %lld)",
+                (long long)ws.m);
+  if (mll) *mll = -0.5 * hout[0] - 0.5 * hout[1] - 0.5 * (double)ws.m * std::log(6.283185307179586477);
+  if (grad)
+    for (int k = 0; k < d + 2; ++k) grad[k] = hout[2 + k];
+  return GP_OK;
+}
+
+int nearest_run(gp_ctx* ctx, const float* X, int64_t n, int d, int64_t centre, int64_t k,
+                int64_t* idx) {
+  if (k == 0) return GP_OK;
+  uint64_t* key;
+  SelState* st;
+  int64_t* cnt;
+  CHK(ensure(ctx, B_NRKEY, (size_t)n, &key));
+  CHK(ensure(ctx, B_NRST, 1, &st));
+  CHK(ensure(ctx, B_NRCNT, 2 * (size_t)nearest_blocks(n), &cnt));
+  ProfScope ps(ctx, 6);
+  HIPCHK(nearest(X, n, d, centre, k, key, st, cnt, idx, ctx->stream));
+  return GP_OK;
+}
+
+int check_centre(gp_ctx* ctx, int64_t centre, int64_t n) {
+  if (centre < 0 || centre >= n)
+    return fail(ctx, GP_ERR_INVALID_ARG, "centre %lld outside [0, %lld)", (long long)centre,
+                (long long)n);
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_nearest(gp_ctx* ctx, const float* X, int64_t n, int d, int64_t centre, int64_t k,
+               int64_t* idx) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_dims(ctx, d, 0));
+  if (n < 0) return fail(ctx, GP_ERR_INVALID_ARG, "n < 0");
+  if (k < 0 || k > n)
+    return fail(ctx, GP_ERR_INVALID_ARG, "k = %lld outside [0, n = %lld]", (long long)k,
+                (long long)n);
+  if (k == 0) return GP_OK;
+  CHK(check_centre(ctx, centre, n));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  if (!idx) return fail(ctx, GP_ERR_INVALID_ARG, "idx is NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  return nearest_run(ctx, X, n, d, centre, k, idx);
+}
+
+int gp_exact_mll(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                 const int64_t* idx, int64_t m, const double* theta, double* mll, double* grad) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  CHK(check_dims(ctx, d, 0));
+  CHK(check_theta(ctx, theta, d));
+  if (m < 1 || m > kExactMaxM)
+    return fail(ctx, GP_ERR_INVALID_ARG, "m = %lld outside [1, %lld]", (long long)m,
+                (long long)kExactMaxM);
+  if (n < 1) return fail(ctx, GP_ERR_INVALID_ARG, "n < 1");
+  if (!idx && m > n)
+    return fail(ctx, GP_ERR_INVALID_ARG, "m = %lld > n = %lld without an index list",
+                (long long)m, (long long)n);
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "y", y, n, 1, 1));
+  HIPCHK(hipSetDevice(ctx->device));
+  ExactWs ws;
+  CHK(exact_prepare(ctx, X, n, d, y, idx, m, ws));
+  return exact_run(ctx, ws, theta, mll, grad);
+}
+
+void gp_init_cfg_default(gp_init_cfg* cfg) {
+  if (!cfg) return;
+  cfg->steps = 100;
+  cfg->lr = 0.1;
+  cfg->transform = GP_SOFTPLUS;
+  cfg->theta0 = nullptr;
+}
+
+int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
+                      const int64_t* centres, int nc, int64_t m, const gp_init_cfg* cfg_in,
+                      double* theta_out, double* theta_each) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  gp_init_cfg cfg;
+  gp_init_cfg_default(&cfg);
+  if (cfg_in) cfg = *cfg_in;
+  CHK(check_dims(ctx, d, 0));
+  if (nc < 1 || !centres) return fail(ctx, GP_ERR_INVALID_ARG, "need nc >= 1 centre rows");
+  if (!theta_out) return fail(ctx, GP_ERR_INVALID_ARG, "theta_out is NULL");
+  if (m < 1 || m > n || m > kExactMaxM)
+    return fail(ctx, GP_ERR_INVALID_ARG, "m = %lld outside [1, min(n, %lld)]", (long long)m,
+                (long long)kExactMaxM);
+  if (cfg.steps < 0 || !(cfg.lr > 0.0) || !std::isfinite(cfg.lr))
+    return fail(ctx, GP_ERR_INVALID_ARG, "steps must be >= 0 and lr > 0");
+  if (cfg.transform != GP_SOFTPLUS && cfg.transform != GP_LOG)
+    return fail(ctx, GP_ERR_INVALID_ARG, "unknown transform %d", cfg.transform);
+  if (cfg.theta0) CHK(check_theta(ctx, cfg.theta0, d));
+  for (int c = 0; c < nc; ++c) CHK(check_centre(ctx, centres[c], n));
+  CHK(check_mat(ctx, "X", X, n, d, d));
+  CHK(check_mat(ctx, "y", y, n, 1, 1));
+  HIPCHK(hipSetDevice(ctx->device));
+  const int p = d + 2;
+  int64_t* idx;
+  CHK(ensure(ctx, B_NRIDX, (size_t)m, &idx));
+  std::vector<double> nu(p), mom(p), vel(p), th(p), g(p), sum(p, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    CHK(nearest_run(ctx, X, n, d, centres[c], m, idx));
+    ExactWs ws;
+    CHK(exact_prepare(ctx, X, n, d, y, idx, m, ws));
+    for (int k = 0; k < p; ++k) {
+      const double t0 = cfg.theta0 ? cfg.theta0[k] : 1.0;
+      nu[k] = cfg.transform == GP_LOG ? std::log(t0) : t0 + std::log(-std::expm1(-t0));
+      mom[k] = vel[k] = 0.0;
+    }
+    int64_t step = 0;
+    for (int it = 0; it < cfg.steps; ++it) {
+      gp_nu_to_theta(p, nu.data(), cfg.transform, th.data());
+      CHK(exact_run(ctx, ws, th.data(), nullptr, g.data()));
+      gp_adam_ascent(p, nu.data(), mom.data(), vel.data(), &step, g.data(), cfg.lr,
+                     cfg.transform);
+    }
+    gp_nu_to_theta(p, nu.data(), cfg.transform, th.data());
+    for (int k = 0; k < p; ++k) {
+      if (!std::isfinite(th[k]) || !(th[k] > 0.0))
+        return fail(ctx, GP_ERR_NONFINITE, "theta[%d] = %g after the maximisation for centre %d",
+                    k, th[k], c);
+      sum[k] += th[k];
+      if (theta_each) theta_each[(int64_t)c * p + k] = th[k];
+    }
+  }
+  for (int k = 0; k < p; ++k) theta_out[k] = sum[k] / nc;
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -64,3 +64,11 @@ def test_host_only_entry_points_without_gpu():
     np.testing.assert_allclose(x, xr, rtol=1e-12)
     assert step.value == 5
     assert L.gp_adam_ascent(-1, None, None, None, C.byref(step), None, 0.1, 0) == N.GP_ERR_INVALID_ARG
+
+
+def test_init_cfg_default_is_the_small_data_setting():
+    import ctypes as C
+    cfg = N.InitCfg()
+    N.lib().gp_init_cfg_default(C.byref(cfg))
+    assert cfg.steps == 100 and cfg.lr == 0.1 and cfg.transform == N.GP_SOFTPLUS
+    assert not cfg.theta0
