@@ -95,7 +95,9 @@ const char* gp_version(void);
  *   2 = random-feature sample, 3 = CG vector updates, 4 = forward product kernel
  *   in GP_FP32 (classes 0 and 4 time the product kernel alone, not the sum of
  *   its column-split partials), 5 = CG preconditioner (construction and apply),
- *   6 = initial-hyperparameter heuristic (nearest rows, exact likelihood).
+ *   6 = nearest-row selection, 7 = exact-likelihood factorisation (H, its
+ *   Cholesky factor and inverse, H^-1: FP64 GEMMs and leaf blocks), 8 = the rest
+ *   of the exact likelihood (alpha, gradient contraction).
  * Errors: GP_ERR_INVALID_ARG for an unknown class.                          */
 int gp_profile_enable(gp_ctx* ctx, int enable);
 int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches);

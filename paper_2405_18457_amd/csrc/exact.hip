@@ -83,56 +83,78 @@ __global__ __launch_bounds__(256) void kex_build(const double* __restrict__ xs, 
   }
 }
 
-// Leaf of the recursion: the 64 x 64 diagonal block at (off, off).  Cholesky of
-// its lower triangle in LDS (status bit 2 on a non-positive pivot, which is then
-// replaced by 1 so the kernel completes), the pivots C_ii into diag, and the
-// inverse factor into W's block (upper part zero): one wave per column j, lane
-// i holding W_ij = -(sum_{j<=t<i} C_it W_tj) / C_ii, accumulated as the W_tj
-// become known (lane shuffles).
-__global__ __launch_bounds__(256) void kex_leaf(const double* __restrict__ A, double* __restrict__ W,
-                                                int64_t ld, int64_t off, double* __restrict__ diag,
-                                                int* __restrict__ status) {
-  __shared__ double Lt[kET][kET + 1];
-  __shared__ double inv[kET];
-  __shared__ int bad;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < kET * kET; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    Lt[i][j] = (j <= i) ? A[(off + i) * ld + off + j] : 0.0;
-  }
-  __syncthreads();
+__device__ __forceinline__ double rdlane(double v, int k) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, k);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// 1/sqrt(p) for p > 0: hardware estimate and two Newton steps r <- r (3 - p r^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double p) {
+  double r = __builtin_amdgcn_rsq(p);
+  r = r * (1.5 - 0.5 * p * r * r);
+  return r * (1.5 - 0.5 * p * r * r);
+}
+
+// Leaf of the recursion: the 64 x 64 diagonal block at (off, off), one wave,
+// lane r holding row r in registers (every loop below is unrolled, so all
+// register indices are static).  No barriers: the wave's LDS accesses complete
+// in order, and each column is broadcast through LDS.
+// Cholesky, step k: pivot from lane k, lanes below scale their entry of column k,
+// which every lane then reads to update its entries right of k
+// (C_rc -= C_rk C_ck).  A non-positive pivot sets status bit 2 and is replaced
+// by 1 so the kernel completes; the pivots go to diag.
+// Inverse factor: lane c forms column c of W = C^-1 by forward substitution,
+// x_s = (delta_sc - acc_s) / C_ss, then acc_r += C_rs x_s for r > s, with
+// column s of C broadcast the same way; columns left of c stay exactly zero.
+__global__ __launch_bounds__(64) void kex_leaf(const double* __restrict__ A, double* __restrict__ W,
+                                               int64_t ld, int64_t off, double* __restrict__ diag,
+                                               int* __restrict__ status) {
+  __shared__ double colb[kET];
+  const int r = threadIdx.x;
+  double dr[kET];
+#pragma unroll
+  for (int c = 0; c < kET; ++c) dr[c] = (c <= r) ? A[(off + r) * ld + off + c] : 0.0;
+  bool bad = false;
+  double mydiag = 1.0, myinv = 1.0;
+#pragma unroll
   for (int k = 0; k < kET; ++k) {
-    if (tid == 0) {
-      const double p = Lt[k][k];
-      if (!(p > 0.0)) bad = 1;
-      Lt[k][k] = p > 0.0 ? sqrt(p) : 1.0;
+    double p = rdlane(dr[k], k);
+    if (!(p > 0.0)) {
+      bad = true;
+      p = 1.0;
     }
-    __syncthreads();
-    if (tid > k && tid < kET) Lt[tid][k] /= Lt[k][k];
-    __syncthreads();
-    for (int e = tid; e < kET * kET; e += 256) {
-      const int i = e >> 6, j = e & 63;
-      if (j > k && i >= j) Lt[i][j] -= Lt[i][k] * Lt[j][k];
+    const double ri = rsqrt_nr(p);
+    const double sk = p * ri;
+    if (r == k) {
+      mydiag = sk;
+      myinv = ri;
     }
-    __syncthreads();
+    dr[k] = r > k ? dr[k] * ri : (r == k ? sk : dr[k]);
+    colb[r] = dr[k];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = k + 1; c < kET; ++c) dr[c] = __builtin_fma(-dr[k], colb[c], dr[c]);
+    __builtin_amdgcn_wave_barrier();
   }
-  if (tid < kET) {
-    diag[off + tid] = Lt[tid][tid];
-    inv[tid] = 1.0 / Lt[tid][tid];
+  diag[off + r] = mydiag;
+  // column r of W (lane r computes column c = r)
+  double x[kET];
+#pragma unroll
+  for (int s2 = 0; s2 < kET; ++s2) x[s2] = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < kET; ++s2) {
+    x[s2] = ((r == s2 ? 1.0 : 0.0) - x[s2]) * rdlane(myinv, s2);
+    colb[r] = dr[s2];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int rr = s2 + 1; rr < kET; ++rr) x[rr] = __builtin_fma(colb[rr], x[s2], x[rr]);
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
-  for (int j = wave; j < kET; j += 4) {
-    double s = 0.0, wij = 0.0;
-    for (int k = j; k < kET; ++k) {
-      const double sk = __shfl(s, k, 64);
-      const double wk = (k == j) ? inv[j] : -sk * inv[k];
-      if (lane == k) wij = wk;
-      if (lane > k) s += Lt[lane][k] * wk;
-    }
-    W[(off + lane) * ld + off + j] = lane >= j ? wij : 0.0;
-  }
-  if (tid == 0 && bad) atomicOr(status, 2);
+#pragma unroll
+  for (int rr = 0; rr < kET; ++rr) W[(off + rr) * ld + off + r] = x[rr];
+  if (r == 0 && bad) atomicOr(status, 2);
 }
 
 // C (M x N) = alpha op(A) op(B) (+ C when accumulate).  op(A)[i][k] = A[i*lda + k]
@@ -337,16 +359,19 @@ __global__ __launch_bounds__(256) void kex_grad(const double* __restrict__ xs, i
   if (tid < d + 2) part[tile * (d + 2) + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
-// grad[k] from the tile partials in tile order; scal = (a, sigma).
+// grad[k] from the tile partials: one workgroup per component k, thread t summing
+// tiles t, t + 256, ... in order, then a fixed tree (deterministic).
 __global__ __launch_bounds__(256) void kex_grad_final(const double* __restrict__ part,
                                                       int64_t ntiles, int d,
                                                       const double* __restrict__ inv_ell,
                                                       double a, double sigma,
                                                       double* __restrict__ grad) {
-  const int k = threadIdx.x;
-  if (k >= d + 2) return;
+  __shared__ double red[4];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int64_t t = 0; t < ntiles; ++t) s += part[t * (d + 2) + k];
+  for (int64_t t = threadIdx.x; t < ntiles; t += 256) s += part[t * (d + 2) + k];
+  s = block_sum(s, red);
+  if (threadIdx.x != 0) return;
   double g;
   if (k < d) {
     const double il = inv_ell[k];
@@ -383,7 +408,7 @@ hipError_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const double*
 hipError_t chol_inv(double* A, double* W, int64_t ld, int64_t off, int64_t m, double* diag,
                     int* status, hipStream_t st) {
   if (m == kET) {
-    hipLaunchKernelGGL(kex_leaf, dim3(1), dim3(256), 0, st, A, W, ld, off, diag, status);
+    hipLaunchKernelGGL(kex_leaf, dim3(1), dim3(64), 0, st, A, W, ld, off, diag, status);
     return hipGetLastError();
   }
   const int64_t m1 = kET * ((m / kET + 1) / 2), m2 = m - m1;
@@ -420,16 +445,26 @@ hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, in
   return hipGetLastError();
 }
 
-hipError_t exact_eval(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
-                      const double* inv_ell, double a, double sigma, double* A, double* W,
-                      double* diag, double* v, double* alpha, double* part, double* gpart,
-                      double* out, int* status, hipStream_t st) {
+hipError_t exact_factor(const double* xs, int d, int64_t m, int64_t mp, const double* inv_ell,
+                        double a, double sigma, double* A, double* W, double* diag, int* status,
+                        hipStream_t st) {
   if (mp % kET || mp < m) return hipErrorInvalidValue;
   const unsigned T = (unsigned)(mp / kET);
   hipLaunchKernelGGL(kex_build, dim3(T, T), dim3(256), 0, st, xs, d, m, mp, inv_ell, a * a,
                      sigma * sigma, A);
   hipError_t e = chol_inv(A, W, mp, 0, mp, diag, status, st);
   if (e != hipSuccess) return e;
+  // H^-1 = W^T W into A (lower tiles; op(A) = W^T upper, op(B) = W lower)
+  return gemm(true, false, mp, mp, mp, W, mp, W, mp, A, mp, 1.0, false,
+              kExLowerC | kExAUpper | kExBLower, st);
+}
+
+hipError_t exact_finish(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
+                        const double* inv_ell, double a, double sigma, const double* Hinv,
+                        const double* W, const double* diag, double* v, double* alpha,
+                        double* part, double* gpart, double* out, hipStream_t st) {
+  if (mp % kET || mp < m) return hipErrorInvalidValue;
+  const unsigned T = (unsigned)(mp / kET);
   // alpha = W^T (W y)
   hipLaunchKernelGGL(kex_wy, dim3((unsigned)((mp + 3) / 4)), dim3(256), 0, st, W, mp, ys, v);
   const int nc = (int)((mp + kExactChunk - 1) / kExactChunk);
@@ -438,13 +473,9 @@ hipError_t exact_eval(const double* xs, const double* ys, int d, int64_t m, int6
   hipLaunchKernelGGL(kex_sum_parts, dim3((unsigned)((mp + 255) / 256)), dim3(256), 0, st, part, nc,
                      mp, alpha);
   hipLaunchKernelGGL(kex_scalars, dim3(1), dim3(256), 0, st, ys, alpha, diag, m, out);
-  // H^-1 = W^T W into A (lower tiles; op(A) = W^T upper, op(B) = W lower)
-  e = gemm(true, false, mp, mp, mp, W, mp, W, mp, A, mp, 1.0, false,
-           kExLowerC | kExAUpper | kExBLower, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kex_grad, dim3(T, T), dim3(256), 0, st, xs, d, m, mp, inv_ell, A, alpha,
+  hipLaunchKernelGGL(kex_grad, dim3(T, T), dim3(256), 0, st, xs, d, m, mp, inv_ell, Hinv, alpha,
                      gpart);
-  hipLaunchKernelGGL(kex_grad_final, dim3(1), dim3(256), 0, st, gpart,
+  hipLaunchKernelGGL(kex_grad_final, dim3((unsigned)(d + 2)), dim3(256), 0, st, gpart,
                      (int64_t)T * (T + 1) / 2, d, inv_ell, a, sigma, out + 2);
   return hipGetLastError();
 }

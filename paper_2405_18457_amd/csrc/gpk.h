@@ -302,10 +302,15 @@ enum ExFlags { kExLowerC = 1, kExALower = 2, kExAUpper = 4, kExBLower = 8, kExBU
 hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, int64_t m,
                         int64_t mp, const float* y, double* xs, double* ys, int* status,
                         hipStream_t st);
-hipError_t exact_eval(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
-                      const double* inv_ell, double a, double sigma, double* A, double* W,
-                      double* diag, double* v, double* alpha, double* part, double* gpart,
-                      double* out, int* status, hipStream_t st);
+// exact_factor: H (lower tiles), the recursive Cholesky with inverse factor W, and
+// H^-1 = W^T W into A.  exact_finish: alpha = W^T W y, the scalars and the gradient.
+hipError_t exact_factor(const double* xs, int d, int64_t m, int64_t mp, const double* inv_ell,
+                        double a, double sigma, double* A, double* W, double* diag, int* status,
+                        hipStream_t st);
+hipError_t exact_finish(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
+                        const double* inv_ell, double a, double sigma, const double* Hinv,
+                        const double* W, const double* diag, double* v, double* alpha,
+                        double* part, double* gpart, double* out, hipStream_t st);
 int64_t exact_part_doubles(int64_t mp);
 int64_t exact_gpart_doubles(int64_t mp, int d);
 

@@ -33,7 +33,7 @@ enum BufId {
 
 constexpr double kNormEps = 1e-10;
 constexpr int64_t kSafetyCap = 100000;
-constexpr int kProfClasses = 7;
+constexpr int kProfClasses = 9;
 
 struct Packed {
   float* xp = nullptr;  // [n_pad, DP] scaled points
@@ -393,6 +393,15 @@ struct Progress {
     last = now;
     std::fprintf(stderr, "[gpmi] %s iter %lld  relres_y %.3e  relres_z %.3e  (%.1f s)\n", what,
                  (long long)it, ry, rz, std::chrono::duration<double>(now - start).count());
+    std::fflush(stderr);
+  }
+  void count(const char* what, int64_t done, int64_t total) {
+    if (every <= 0.0) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double>(now - last).count() < every && done < total) return;
+    last = now;
+    std::fprintf(stderr, "[gpmi] %s %lld/%lld  (%.1f s)\n", what, (long long)done,
+                 (long long)total, std::chrono::duration<double>(now - start).count());
     std::fflush(stderr);
   }
 };
@@ -1442,10 +1451,14 @@ int exact_run(gp_ctx* ctx, const ExactWs& ws, const double* theta, double* mll, 
   for (int k = 0; k < d; ++k) hin[k] = 1.0 / theta[k];
   HIPCHK(hipMemcpyAsync(ws.inv_ell, hin, d * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   {
-    ProfScope ps(ctx, 6);
-    HIPCHK(exact_eval(ws.xs, ws.ys, d, ws.m, ws.mp, ws.inv_ell, theta[d], theta[d + 1], ws.A, ws.W,
-                      ws.diag, ws.v, ws.alpha, ws.part, ws.gpart, ws.out, ws.status,
-                      ctx->stream));
+    ProfScope ps(ctx, 7);
+    HIPCHK(exact_factor(ws.xs, d, ws.m, ws.mp, ws.inv_ell, theta[d], theta[d + 1], ws.A, ws.W,
+                        ws.diag, ws.status, ctx->stream));
+  }
+  {
+    ProfScope ps(ctx, 8);
+    HIPCHK(exact_finish(ws.xs, ws.ys, d, ws.m, ws.mp, ws.inv_ell, theta[d], theta[d + 1], ws.A,
+                        ws.W, ws.diag, ws.v, ws.alpha, ws.part, ws.gpart, ws.out, ctx->stream));
   }
   HIPCHK(hipMemcpyAsync(hout, ws.out, (d + 4) * sizeof(double), hipMemcpyDeviceToHost,
                         ctx->stream));
@@ -1561,6 +1574,7 @@ int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float
   int64_t* idx;
   CHK(ensure(ctx, B_NRIDX, (size_t)m, &idx));
   std::vector<double> nu(p), mom(p), vel(p), th(p), g(p), sum(p, 0.0);
+  Progress pr;
   for (int c = 0; c < nc; ++c) {
     CHK(nearest_run(ctx, X, n, d, centres[c], m, idx));
     ExactWs ws;
@@ -1585,6 +1599,7 @@ int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float
       sum[k] += th[k];
       if (theta_each) theta_each[(int64_t)c * p + k] = th[k];
     }
+    pr.count("init heuristic: centres done", c + 1, nc);
   }
   for (int k = 0; k < p; ++k) theta_out[k] = sum[k] / nc;
   return GP_OK;
