@@ -405,8 +405,18 @@ hipError_t gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const double*
 
 // Factor the diagonal block [off, off + m) of A (its trailing updates done) and
 // write its inverse factor into the same block of W (see the file comment).
+// With a side stream, T = C21 W11 (which needs only C21 and W11) runs there,
+// concurrently with the update of A22 and its factorisation on the main stream;
+// W21 = -W22 T waits for it.  Two events per split, taken from ev in order.
+struct ExStreams {
+  hipStream_t main, side;
+  hipEvent_t* ev;
+  int nev, used;
+};
+
 hipError_t chol_inv(double* A, double* W, int64_t ld, int64_t off, int64_t m, double* diag,
-                    int* status, hipStream_t st) {
+                    int* status, ExStreams& xs) {
+  hipStream_t st = xs.main;
   if (m == kET) {
     hipLaunchKernelGGL(kex_leaf, dim3(1), dim3(64), 0, st, A, W, ld, off, diag, status);
     return hipGetLastError();
@@ -418,20 +428,36 @@ hipError_t chol_inv(double* A, double* W, int64_t ld, int64_t off, int64_t m, do
   double* W21 = W + (off + m1) * ld + off;
   double* W22 = W + (off + m1) * ld + off + m1;
   hipError_t e;
-  if ((e = chol_inv(A, W, ld, off, m1, diag, status, st)) != hipSuccess) return e;
+  if ((e = chol_inv(A, W, ld, off, m1, diag, status, xs)) != hipSuccess) return e;
   // C21 = A21 W11^T (op(B) = W11^T is upper triangular) -> W21 slot
   if ((e = gemm(false, true, m2, m1, m1, A21, ld, W11, ld, W21, ld, 1.0, false, kExBUpper, st)) !=
       hipSuccess)
     return e;
+  const bool overlap = xs.side && xs.used + 2 <= xs.nev;
+  hipEvent_t e_c21 = nullptr, e_t = nullptr;
+  if (overlap) {
+    e_c21 = xs.ev[xs.used++];
+    e_t = xs.ev[xs.used++];
+    if ((e = hipEventRecord(e_c21, st)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(xs.side, e_c21, 0)) != hipSuccess) return e;
+    // T = C21 W11 (W11 lower) -> A21 slot, on the side stream
+    if ((e = gemm(false, false, m2, m1, m1, W21, ld, W11, ld, A21, ld, 1.0, false, kExBLower,
+                  xs.side)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(e_t, xs.side)) != hipSuccess) return e;
+  }
   // A22 -= C21 C21^T, lower tiles
   if ((e = gemm(false, true, m2, m2, m1, W21, ld, W21, ld, A22, ld, -1.0, true, kExLowerC, st)) !=
       hipSuccess)
     return e;
-  if ((e = chol_inv(A, W, ld, off + m1, m2, diag, status, st)) != hipSuccess) return e;
-  // T = C21 W11 (W11 lower) -> A21 slot;  W21 = -W22 T (W22 lower)
-  if ((e = gemm(false, false, m2, m1, m1, W21, ld, W11, ld, A21, ld, 1.0, false, kExBLower, st)) !=
-      hipSuccess)
+  if ((e = chol_inv(A, W, ld, off + m1, m2, diag, status, xs)) != hipSuccess) return e;
+  if (overlap) {
+    if ((e = hipStreamWaitEvent(st, e_t, 0)) != hipSuccess) return e;
+  } else if ((e = gemm(false, false, m2, m1, m1, W21, ld, W11, ld, A21, ld, 1.0, false, kExBLower,
+                       st)) != hipSuccess) {
     return e;
+  }
+  // W21 = -W22 T (W22 lower)
   return gemm(false, false, m2, m1, m2, W22, ld, A21, ld, W21, ld, -1.0, false, kExALower, st);
 }
 
@@ -447,12 +473,13 @@ hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, in
 
 hipError_t exact_factor(const double* xs, int d, int64_t m, int64_t mp, const double* inv_ell,
                         double a, double sigma, double* A, double* W, double* diag, int* status,
-                        hipStream_t st) {
+                        hipStream_t st, hipStream_t side, hipEvent_t* ev, int nev) {
   if (mp % kET || mp < m) return hipErrorInvalidValue;
   const unsigned T = (unsigned)(mp / kET);
   hipLaunchKernelGGL(kex_build, dim3(T, T), dim3(256), 0, st, xs, d, m, mp, inv_ell, a * a,
                      sigma * sigma, A);
-  hipError_t e = chol_inv(A, W, mp, 0, mp, diag, status, st);
+  ExStreams xst{st, side, ev, nev, 0};
+  hipError_t e = chol_inv(A, W, mp, 0, mp, diag, status, xst);
   if (e != hipSuccess) return e;
   // H^-1 = W^T W into A (lower tiles; op(A) = W^T upper, op(B) = W lower)
   return gemm(true, false, mp, mp, mp, W, mp, W, mp, A, mp, 1.0, false,

@@ -303,10 +303,14 @@ hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, in
                         int64_t mp, const float* y, double* xs, double* ys, int* status,
                         hipStream_t st);
 // exact_factor: H (lower tiles), the recursive Cholesky with inverse factor W, and
-// H^-1 = W^T W into A.  exact_finish: alpha = W^T W y, the scalars and the gradient.
+// H^-1 = W^T W into A, on stream st; with a side stream (may be null) and
+// exact_events(m_p) events, part of each split runs concurrently on it, joined
+// back into st before return.  exact_finish: alpha = W^T W y, the scalars and
+// the gradient.
 hipError_t exact_factor(const double* xs, int d, int64_t m, int64_t mp, const double* inv_ell,
                         double a, double sigma, double* A, double* W, double* diag, int* status,
-                        hipStream_t st);
+                        hipStream_t st, hipStream_t side, hipEvent_t* ev, int nev);
+inline int exact_events(int64_t mp) { return 2 * (int)(mp / kExactTile); }
 hipError_t exact_finish(const double* xs, const double* ys, int d, int64_t m, int64_t mp,
                         const double* inv_ell, double a, double sigma, const double* Hinv,
                         const double* W, const double* diag, double* v, double* alpha,

@@ -51,6 +51,8 @@ struct gp_ctx {
   hipStream_t stream = nullptr;
   hipStream_t gstream = nullptr;  // library-owned stream for captured solver iterations
   hipEvent_t gev[2] = {nullptr, nullptr};
+  hipStream_t xstream = nullptr;  // library-owned side stream of the exact factorisation
+  std::vector<hipEvent_t> xev;    // its dependency events
   uint64_t alloc_epoch = 0;       // bumped on every workspace (re)allocation
   std::string err;
   void* buf[B_COUNT] = {};
@@ -949,6 +951,11 @@ void gp_ctx_destroy(gp_ctx* ctx) {
   }
   for (auto e : ctx->gev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->xstream) {
+    (void)hipStreamSynchronize(ctx->xstream);
+    (void)hipStreamDestroy(ctx->xstream);
+  }
+  for (auto e : ctx->xev) (void)hipEventDestroy(e);
   for (int i = 0; i < B_COUNT; ++i)
     if (ctx->buf[i]) (void)hipFree(ctx->buf[i]);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
@@ -1450,10 +1457,17 @@ int exact_run(gp_ctx* ctx, const ExactWs& ws, const double* theta, double* mll, 
   double* hout = ctx->hpin + kMaxD;
   for (int k = 0; k < d; ++k) hin[k] = 1.0 / theta[k];
   HIPCHK(hipMemcpyAsync(ws.inv_ell, hin, d * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  if (!ctx->xstream) HIPCHK(hipStreamCreateWithFlags(&ctx->xstream, hipStreamNonBlocking));
+  while ((int)ctx->xev.size() < exact_events(ws.mp)) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->xev.push_back(e);
+  }
   {
     ProfScope ps(ctx, 7);
     HIPCHK(exact_factor(ws.xs, d, ws.m, ws.mp, ws.inv_ell, theta[d], theta[d + 1], ws.A, ws.W,
-                        ws.diag, ws.status, ctx->stream));
+                        ws.diag, ws.status, ctx->stream, ctx->xstream, ctx->xev.data(),
+                        (int)ctx->xev.size()));
   }
   {
     ProfScope ps(ctx, 8);
