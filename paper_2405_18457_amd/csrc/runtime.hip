@@ -40,7 +40,7 @@ struct Packed {
   float* xt = nullptr;  // cross-term layout [xt_chunks(d)][n_pad][4] (== xp for d <= 3)
   int64_t n = 0, n_pad = 0;
   int D = 0, DP = 0;
-  bool xt_ok = false;  // max |x^|^2 small enough for the cross-term path (bf16 modes)
+  bool xt_ok = false;  // norms small enough for the cross-term path (bf16 modes)
   bool xt_ok32 = false;  // ... and for the FP32 mode
 };
 
@@ -232,21 +232,23 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
   } else {
     p->xt = p->xp;  // the cross-term layout is the packed layout (DP = 4, norm in slot 3)
   }
-  // squared norms ride in the last slot of the cross-term layout; their maximum
-  // decides whether the cross-term distance form is accurate enough for these points
+  // squared norms ride in the last slot of the cross-term layout; their maximum and
+  // the count above the bulk bound decide whether the cross-term distance form is
+  // accurate enough for these points
   unsigned* mx;
-  CHK(ensure(ctx, B_XTMAX, 1, &mx));
+  CHK(ensure(ctx, B_XTMAX, 2, &mx));
   CHK(ensure_pinned(ctx, 1));
-  HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), ctx->stream));
+  HIPCHK(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned), ctx->stream));
   // chunks for the kernel's dimension tier D (>= d), so kernel and layout agree
   HIPCHK(pack_x_aug(X, idx, n, d, sc, xt_chunks(p->D), p->xt, p->n_pad, mx, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->hpin, mx, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->hpin, mx, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+                        ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  unsigned bits;
-  std::memcpy(&bits, ctx->hpin, sizeof(unsigned));
+  unsigned st[2];
+  std::memcpy(st, ctx->hpin, sizeof st);
   float m;
-  std::memcpy(&m, &bits, sizeof(float));
-  p->xt_ok = std::isfinite(m) && m <= kXTMaxNorm2;
+  std::memcpy(&m, &st[0], sizeof(float));
+  p->xt_ok = std::isfinite(m) && m <= kXTHardNorm2 && (int64_t)st[1] * kXTOutlierShare <= n;
   p->xt_ok32 = std::isfinite(m) && m <= kXTMaxNorm2F32;
   return GP_OK;
 }

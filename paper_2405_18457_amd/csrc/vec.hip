@@ -41,7 +41,7 @@ __global__ void kpack_x(const float* __restrict__ X, const int32_t* __restrict__
 // zeros elsewhere and on padding rows.  The maximum |x^|^2 goes to maxbits.
 __global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restrict__ idx,
                             int64_t n, int d, DimScale sc, int nk, float* __restrict__ Xp,
-                            int64_t n_pad, unsigned* __restrict__ maxbits) {
+                            int64_t n_pad, unsigned* __restrict__ stats) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n_pad) return;
   const int64_t src = i < n ? (idx ? (int64_t)idx[i] : i) : 0;
@@ -61,7 +61,10 @@ __global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restri
     }
     reinterpret_cast<float4*>(Xp)[q * n_pad + i] = make_float4(v[0], v[1], v[2], v[3]);
   }
-  if (maxbits && i < n) atomicMax(maxbits, __builtin_bit_cast(unsigned, nn));
+  if (stats && i < n) {
+    atomicMax(stats, __builtin_bit_cast(unsigned, nn));
+    if (!(nn <= kXTMaxNorm2)) atomicAdd(stats + 1, 1u);
+  }
 }
 
 // Position of row j (within a 32-row tile) on the MFMA contraction index when the
@@ -421,9 +424,9 @@ hipError_t pack_x_rows(const float* X, const int32_t* idx, int64_t nidx, int d, 
 }
 
 hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, const DimScale& sc,
-                      int nk, float* Xp, int64_t n_pad, unsigned* maxbits, hipStream_t st) {
+                      int nk, float* Xp, int64_t n_pad, unsigned* stats, hipStream_t st) {
   hipLaunchKernelGGL(kpack_x_aug, dim3(blocks_for(n_pad)), dim3(kThreads), 0, st, X, idx, n, d, sc,
-                     nk, Xp, n_pad, maxbits);
+                     nk, Xp, n_pad, stats);
   return hipGetLastError();
 }
 

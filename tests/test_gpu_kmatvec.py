@@ -152,3 +152,32 @@ def test_low_dimension_distance_forms(gp, prec, shift_rows, shift_cols):
     else:
         err = col_relerr(out, ref)
     assert err <= TOL[prec], err
+
+@pytest.mark.parametrize("name,prec", [("B", 0), ("B", 1), ("C", 1), ("E", 1)],
+                         ids=["B-fp32", "B-bf16x3", "C-bf16x3", "E-bf16x3"])
+def test_full_size_workloads_sampled_rows(gp, name, prec):
+    """The other workloads at full size and their data-generating hyperparameters
+    (B: n = 16,384, d = 24; C: n = 45,730, d = 9; E: n = 2,049,280, d = 11), 65
+    columns; sampled output rows against FP64 row products.  At B and E a few
+    points exceed the bulk norm bound of the cross-term form (2 and 474 of them)."""
+    import time
+
+    import torch
+    import workloads as wl
+    from paper_2405_18457_amd import api
+    w = wl.WORKLOADS[name]
+    X = wl.draw_inputs(w)
+    theta = np.concatenate([wl.draw_true_lengthscales(w), [1.0, w.sigma]])
+    V = wl.draw_normal(np.random.default_rng(13), (w.n, 65))
+    announce("kmatvec-full", name, prec)
+    Xd, Vd = dev(X), dev(V)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out_d = api.gp_kmatvec(gp, Xd, Xd, theta, Vd, precision=prec, add_noise=True)
+    torch.cuda.synchronize()
+    print(f"[gpu-case] {name} product {1e3 * (time.perf_counter() - t0):.1f} ms", flush=True)
+    rows = np.random.default_rng(14).choice(w.n, 96, replace=False)
+    out = host(out_d[torch.from_numpy(rows).cuda()])
+    ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
+    err = col_relerr(out, ref)
+    assert err <= TOL[prec], err
