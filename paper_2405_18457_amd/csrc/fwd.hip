@@ -35,6 +35,9 @@
 // The step loop is unrolled by two with swapped register buffers (no register
 // copies); the next step's coordinates are loaded at the start of a step and
 // each V tile is reloaded for the next step right after its last MFMA use.
+// The direct kernels pin the MFMA/VALU alternation with scheduling groups; the
+// cross-term kernel leaves the order inside a half-step to the compiler, which
+// measured 2.8 % faster at d = 3 than groups of 1 MFMA : 4 VALU.
 //
 // Accuracy: a fresh accumulator per chunk of kChunk column steps is folded
 // into a running total (two-level summation keeps FP32 chains short at large n).
@@ -423,7 +426,6 @@ __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS][NK], const fl
                                              const float* __restrict__ xnext, int64_t cstride,
                                              int g, const uint16_t* __restrict__ vh_next,
                                              const uint16_t* __restrict__ vl_next) {
-  constexpr int NM = (MODE == P_BF16X3 ? 3 : 1) * CT;
   float rl[NK], rh[NK];
   load_cols_xt<NK>(xnext, cstride, g, rl, rh);
   bf16x8 ah = a0h, al = a0l;
@@ -432,7 +434,6 @@ __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS][NK], const fl
     bf16x8 nh, nl;
     tile_a_xt<MODE, NK>(bx[r + 1], ni[r + 1], ajl, ajh, nh, nl);
     mfma_tiles<MODE, CT>(acc[r], ah, al, bh, bl);
-    interleave<NM + 2 * NK, 4>();
     __builtin_amdgcn_sched_barrier(0);
     ah = nh;
     al = nl;
@@ -461,7 +462,6 @@ __device__ __forceinline__ void bf16_step_xt(const float (&bx)[RS][NK], const fl
         __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[RS - 1][ct], 0, 0, 0);
     bh[ct] = *reinterpret_cast<const bf16x8*>(vh_next + ct * 512);
   }
-  interleave<NM + 2 * NK, 4>();
   __builtin_amdgcn_sched_barrier(0);
 }
 
