@@ -207,6 +207,7 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
 // Bop(i + 4s + l/16, b0 + 16u + l%16); D lane q: (a0 + 16w + 4q + l/16,
 // b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.
 constexpr int kTI = 32;  // rows i per LDS stage
+static_assert(kTI * 8 == 256, "B-tile loaders map 8 threads to each of the kTI rows");
 
 template <int NBT, int BMODE, typename TL>
 __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
@@ -238,11 +239,14 @@ __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t 
       }
     }
     if (BMODE == 0) {
-      for (int e = tid; e < kTI * NB; e += 256) {
-        const int r = e / NB, cc = e % NB;
-        const int64_t ii = i + r;
-        const int bcol = b0 + cc;
-        Bs[r][cc] = (ii < i1 && bcol < nb) ? (double)R[ii * ldr + bcol] : 0.0;
+      // 8 threads per row of the tile, NB / 8 consecutive columns each
+      constexpr int BPT = NB / 8;
+      const int r = tid >> 3, cb = (tid & 7) * BPT;
+      const int64_t ii = i + r;
+#pragma unroll
+      for (int e = 0; e < BPT; ++e) {
+        const int bcol = b0 + cb + e;
+        Bs[r][cb + e] = (ii < i1 && bcol < nb) ? (double)R[ii * ldr + bcol] : 0.0;
       }
     } else {
       for (int rr = lr; rr < NB; rr += 64) {
@@ -386,10 +390,15 @@ __global__ __launch_bounds__(256) void kpc_apply(const float* __restrict__ L, in
         As[lr][lc + e] = (t < k && ii < n) ? (double)L[(int64_t)t * ldl + ii] : 0.0;
       }
     }
-    for (int e = tid; e < kTI * NB; e += 256) {
-      const int r = e / NB, cc = e % NB;
-      const int t = t0 + r, col = c0 + cc;
-      Bs[r][cc] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
+    {
+      constexpr int BPT = NB / 8;  // 8 threads per row of the tile
+      const int r = tid >> 3, cb = (tid & 7) * BPT;
+      const int t = t0 + r;
+#pragma unroll
+      for (int e = 0; e < BPT; ++e) {
+        const int col = c0 + cb + e;
+        Bs[r][cb + e] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
+      }
     }
     __syncthreads();
 #pragma unroll
