@@ -236,20 +236,20 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
   // the count above the bulk bound decide whether the cross-term distance form is
   // accurate enough for these points
   unsigned* mx;
-  CHK(ensure(ctx, B_XTMAX, 2, &mx));
-  CHK(ensure_pinned(ctx, 1));
-  HIPCHK(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned), ctx->stream));
+  CHK(ensure(ctx, B_XTMAX, 3, &mx));
+  CHK(ensure_pinned(ctx, 2));
+  HIPCHK(hipMemsetAsync(mx, 0, 3 * sizeof(unsigned), ctx->stream));
   // chunks for the kernel's dimension tier D (>= d), so kernel and layout agree
   HIPCHK(pack_x_aug(X, idx, n, d, sc, xt_chunks(p->D), p->xt, p->n_pad, mx, ctx->stream));
-  HIPCHK(hipMemcpyAsync(ctx->hpin, mx, 2 * sizeof(unsigned), hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(ctx->hpin, mx, 3 * sizeof(unsigned), hipMemcpyDeviceToHost,
                         ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  unsigned st[2];
+  unsigned st[3];
   std::memcpy(st, ctx->hpin, sizeof st);
   float m;
   std::memcpy(&m, &st[0], sizeof(float));
   p->xt_ok = std::isfinite(m) && m <= kXTHardNorm2 && (int64_t)st[1] * kXTOutlierShare <= n;
-  p->xt_ok32 = std::isfinite(m) && m <= kXTMaxNorm2F32;
+  p->xt_ok32 = std::isfinite(m) && m <= kXTHardNorm2F32 && (int64_t)st[2] * kXTOutlierShare <= n;
   return GP_OK;
 }
 

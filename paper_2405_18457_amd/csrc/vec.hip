@@ -64,6 +64,7 @@ __global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restri
   if (stats && i < n) {
     atomicMax(stats, __builtin_bit_cast(unsigned, nn));
     if (!(nn <= kXTMaxNorm2)) atomicAdd(stats + 1, 1u);
+    if (!(nn <= kXTMaxNorm2F32)) atomicAdd(stats + 2, 1u);
   }
 }
 
