@@ -375,7 +375,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "row-sharded design is described in DESIGN.md and not run here.", file=sys.stderr)
+              "row-sharded design is documented with the library and not run here.", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
