@@ -39,7 +39,7 @@ class SolverCfg(C.Structure):
         ("ap_block", C.c_int), ("sgd_batch", C.c_int), ("sgd_lr", C.c_double),
         ("sgd_momentum", C.c_double), ("sgd_batches", C.POINTER(C.c_int32)),
         ("sgd_batches_count", C.c_int64), ("sgd_seed", C.c_uint64), ("precond_rank", C.c_int),
-        ("use_graph", C.c_int),
+        ("use_graph", C.c_int), ("precond_reuse", C.c_int),
     ]
 
 

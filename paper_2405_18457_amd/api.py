@@ -100,7 +100,7 @@ def _cols(t):
 def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine_every=0,
                check_every=0, ap_block=1000, sgd_batch=500, sgd_lr=10.0, sgd_momentum=0.9,
                sgd_batches: np.ndarray | None = None, sgd_seed=0, precond_rank=0,
-               use_graph=False) -> SolverCfg:
+               use_graph=False, precond_reuse=0) -> SolverCfg:
     cfg = SolverCfg()
     N.lib().gp_solver_cfg_default(C.byref(cfg))
     cfg.solver, cfg.tol, cfg.max_epochs = solver, tol, max_epochs
@@ -109,6 +109,7 @@ def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine
     cfg.sgd_seed = sgd_seed
     cfg.precond_rank = precond_rank
     cfg.use_graph = int(use_graph)
+    cfg.precond_reuse = int(precond_reuse)
     if sgd_batches is not None:
         arr = np.ascontiguousarray(sgd_batches, dtype=np.int32)
         cfg._batches_keepalive = arr

@@ -84,6 +84,8 @@ hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const floa
                        hipStream_t st);
 hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
                       int CT, float* out, int64_t n_pad, bool perm, hipStream_t st);
+// Order-independent 64-bit fingerprint of x[0..count) added to *out (caller zeroes it).
+hipError_t checksum_f32(const float* x, int64_t count, unsigned long long* out, hipStream_t st);
 // Row-major [n_pad, 32*KT] packs for the adjoint (optional per-column weights).
 hipError_t pack_rows_bf16(const float* U, int64_t n, int64_t ldu, int c, const float* colw,
                           int KT, uint16_t* hi, uint16_t* lo, int64_t n_pad, hipStream_t st);
@@ -251,9 +253,11 @@ hipError_t pc_step(const float* X, int64_t n, int d, const double* ell, double a
                    double* pval, int64_t* pidx, int32_t* piv, hipStream_t st);
 // FP32 copy of the factor, used by the products below.
 hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32, hipStream_t st);
-// A (kp x kp) = sigma^2 I + L^T L on the leading k x k block, identity elsewhere.
+// G (k x k) = L^T L; A (kp x kp) = sigma^2 I + G on the leading k x k block,
+// identity elsewhere.
 hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
-                   int64_t part_cap, double* A, int kp, double s2, hipStream_t st);
+                   int64_t part_cap, double* G, hipStream_t st);
+hipError_t pc_shift(const double* G, int k, double* A, int kp, double s2, hipStream_t st);
 int64_t pc_gram_parts(int64_t n, int k);
 // M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank,
 // a multiple of 32); W (kp x kp) and part (pc_inverse_parts) are scratch.

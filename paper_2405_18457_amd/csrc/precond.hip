@@ -480,7 +480,7 @@ hipError_t pc_to_f32(const double* L, int64_t ldl, int k, int64_t n, float* L32,
 }
 
 hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
-                   int64_t part_cap, double* A, int kp, double s2, hipStream_t st) {
+                   int64_t part_cap, double* G, hipStream_t st) {
   const int64_t xt = (k + 63) / 64, yt = (k + 63) / 64;
   int64_t cs = chunk_rows(n, xt * yt, 2048);
   int64_t nz = (n + cs - 1) / cs;
@@ -491,8 +491,14 @@ hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
   if (k > 0 && n > 0)
     hipLaunchKernelGGL((kpc_tn<4, 1, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n,
                        (const float*)nullptr, (int64_t)0, k, cs, part);
-  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
-                     (int)((k > 0 && n > 0) ? nz : 0), k, k, A, kp, kp, s2, 1);
+  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * k)), dim3(kPcThreads), 0, st, part,
+                     (int)((k > 0 && n > 0) ? nz : 0), k, k, G, k, 0, 0.0, 0);
+  return hipGetLastError();
+}
+
+hipError_t pc_shift(const double* G, int k, double* A, int kp, double s2, hipStream_t st) {
+  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, G, 1, k,
+                     k, A, kp, kp, s2, 1);
   return hipGetLastError();
 }
 

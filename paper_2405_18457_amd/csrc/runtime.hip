@@ -28,7 +28,7 @@ enum BufId {
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
   B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2,
   B_EXA, B_EXW, B_EXXS, B_EXYS, B_EXDG, B_EXV, B_EXAL, B_EXPART, B_EXGP, B_EXOUT, B_EXIE, B_EXST,
-  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_COUNT
+  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_PCG, B_PCSUM, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -52,6 +52,14 @@ struct gp_ctx {
   hipStream_t gstream = nullptr;  // library-owned stream for captured solver iterations
   hipEvent_t gev[2] = {nullptr, nullptr};
   hipStream_t xstream = nullptr;  // library-owned side stream of the exact factorisation
+  // the last pivoted-Cholesky factor (B_PCL32) and its Gram matrix (B_PCG), for reuse
+  struct {
+    const float* X = nullptr;
+    unsigned long long sum = 0;  // fingerprint of X's contents
+    int64_t n = 0;
+    int d = 0, k_req = 0, k = 0, uses = 0;
+    bool valid = false;
+  } pcc;
   std::vector<hipEvent_t> xev;    // its dependency events
   uint64_t alloc_epoch = 0;       // bumped on every workspace (re)allocation
   std::string err;
@@ -202,6 +210,8 @@ int check_precond(gp_ctx* ctx, const gp_solver_cfg& cfg) {
     return fail(ctx, GP_ERR_INVALID_ARG, "the pivoted-Cholesky preconditioner is for CG only");
   if (cfg.use_graph && cfg.solver != GP_CG)
     return fail(ctx, GP_ERR_INVALID_ARG, "graph-captured iterations are for CG only");
+  if (cfg.precond_reuse < 0)
+    return fail(ctx, GP_ERR_INVALID_ARG, "precond_reuse %d must be >= 0", cfg.precond_reuse);
   return GP_OK;
 }
 
@@ -487,8 +497,12 @@ int pc_construct(gp_ctx* ctx, const float* X, int64_t n, int d, const double* th
   return GP_OK;
 }
 
+// P for this solve.  The factor and its Gram matrix G = L^T L are kept in the
+// context; with reuse > 0 a factor built for the same X (pointer and contents
+// fingerprint), n, d and rank serves up to `reuse` later solves, and only
+// sigma^2 I + G is factored again.
 int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, int k_req,
-             Precond& pc) {
+             int reuse, Precond& pc) {
   pc = Precond{};
   pc.n = n;
   pc.s2 = theta[d + 1] * theta[d + 1];
@@ -496,27 +510,63 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   const int k = (int)std::min<int64_t>(k_req, n);
   if (k <= 0) return GP_OK;
   pc.ldl = round_up(n, 64);
-  int32_t* piv;
-  CHK(ensure(ctx, B_PCL32, (size_t)k * pc.ldl, &pc.L32));
-  CHK(ensure(ctx, B_PCPIV, (size_t)k, &piv));
-  CHK(pc_construct(ctx, X, n, d, theta, k, nullptr, pc.L32, pc.ldl, piv, &pc.k));
+  auto& cc = ctx->pcc;
+  unsigned long long sum = 0;
+  {
+    unsigned long long* dsum;
+    CHK(ensure(ctx, B_PCSUM, 1, &dsum));
+    CHK(ensure_pinned(ctx, 1));
+    HIPCHK(hipMemsetAsync(dsum, 0, sizeof(unsigned long long), ctx->stream));
+    HIPCHK(checksum_f32(X, n * d, dsum, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->hpin, dsum, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memcpy(&sum, ctx->hpin, sizeof sum);
+  }
+  const bool again = reuse > 0 && cc.valid && cc.X == X && cc.sum == sum && cc.n == n &&
+                     cc.d == d && cc.k_req == k && cc.uses < reuse;
+  double *part, *G;
+  if (again) {
+    CHK(ensure(ctx, B_PCL32, (size_t)k * pc.ldl, &pc.L32));  // present: no reallocation
+    pc.k = cc.k;
+    ++cc.uses;
+  } else {
+    cc.valid = false;
+    int32_t* piv;
+    CHK(ensure(ctx, B_PCL32, (size_t)k * pc.ldl, &pc.L32));
+    CHK(ensure(ctx, B_PCPIV, (size_t)k, &piv));
+    CHK(pc_construct(ctx, X, n, d, theta, k, nullptr, pc.L32, pc.ldl, piv, &pc.k));
+    if (pc.k == 0) return GP_OK;
+    const int64_t pcap = pc_gram_parts(n, pc.k);
+    CHK(ensure(ctx, B_PCPART, (size_t)pcap, &part));
+    CHK(ensure(ctx, B_PCG, (size_t)pc.k * pc.k, &G));
+    HIPCHK(pc_gram(pc.L32, pc.ldl, pc.k, n, part, pcap, G, ctx->stream));
+    cc.X = X;
+    cc.sum = sum;
+    cc.n = n;
+    cc.d = d;
+    cc.k_req = k;
+    cc.k = pc.k;
+    cc.uses = 0;
+    cc.valid = true;
+  }
   if (pc.k == 0) return GP_OK;
   pc.kp = (int)round_up(pc.k, 32);
-  double *part, *A;
+  double* A;
   int* stat;
-  const int64_t pcap = pc_gram_parts(n, pc.k);
-  CHK(ensure(ctx, B_PCPART, (size_t)pcap, &part));
+  CHK(ensure(ctx, B_PCG, (size_t)pc.k * pc.k, &G));
   CHK(ensure(ctx, B_PCA, (size_t)pc.kp * pc.kp, &A));
   CHK(ensure(ctx, B_PCM, (size_t)pc.kp * pc.kp, &pc.M));
   CHK(ensure(ctx, B_PCSTAT, 1, &stat));
   HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
-  HIPCHK(pc_gram(pc.L32, pc.ldl, pc.k, n, part, pcap, A, pc.kp, pc.s2, ctx->stream));
+  HIPCHK(pc_shift(G, pc.k, A, pc.kp, pc.s2, ctx->stream));
   HIPCHK(chol_blocked(A, pc.kp, stat, ctx->stream));
   double* W;
   CHK(ensure(ctx, B_PCW, (size_t)pc.kp * pc.kp, &W));
   const int64_t icap = pc_inverse_parts(pc.kp);
-  if (icap > pcap) CHK(ensure(ctx, B_PCPART, (size_t)icap, &part));
-  HIPCHK(pc_inverse(A, pc.kp, W, part, std::max(icap, pcap), pc.M, ctx->stream));
+  CHK(ensure(ctx, B_PCPART, (size_t)std::max(icap, pc_gram_parts(n, pc.k)), &part));
+  HIPCHK(pc_inverse(A, pc.kp, W, part, std::max(icap, pc_gram_parts(n, pc.k)), pc.M,
+                    ctx->stream));
   int hst = 0;
   HIPCHK(hipMemcpyAsync(ctx->hpin, stat, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -603,7 +653,7 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
   if (cfg.precond_rank > 0) {
     {
       ProfScope ps(ctx, 5);
-      CHK(pc_build(ctx, X, s.n, d, theta, cfg.precond_rank, pcs));
+      CHK(pc_build(ctx, X, s.n, d, theta, cfg.precond_rank, cfg.precond_reuse, pcs));
     }
     CHK(ensure(ctx, B_Z, (size_t)s.n * s.c, &s.Z));
     pc = &pcs;
@@ -1147,6 +1197,7 @@ void gp_solver_cfg_default(gp_solver_cfg* cfg) {
   cfg->sgd_seed = 0;
   cfg->precond_rank = 0;
   cfg->use_graph = 0;
+  cfg->precond_reuse = 0;
 }
 
 int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta, const float* B,

@@ -408,6 +408,19 @@ __global__ void ksgd_momentum(float* __restrict__ Mom, const float* __restrict__
   }
 }
 
+// Fingerprint of a float array: sum over t of (bits(x_t) + 1) (2t + 1) K mod 2^64,
+// position-dependent and independent of the summation order.
+__global__ void kchecksum(const float* __restrict__ x, int64_t count,
+                          unsigned long long* __restrict__ out) {
+  unsigned long long h = 0;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * kThreads) {
+    const unsigned long long b = __builtin_bit_cast(unsigned, x[t]);
+    h += (b + 1ull) * (2ull * (unsigned long long)t + 1ull) * 0x9E3779B97F4A7C15ull;
+  }
+  atomicAdd(out, h);
+}
+
 }  // namespace
 
 hipError_t pack_x(const float* X, int64_t n, int d, int DP, const DimScale& sc, float* Xp,
@@ -640,6 +653,13 @@ hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* statu
   if (n * c == 0) return hipSuccess;
   hipLaunchKernelGGL(kcheck_finite, dim3(blocks_for(n * c)), dim3(kThreads), 0, st, A, n, ld, c,
                      status);
+  return hipGetLastError();
+}
+
+hipError_t checksum_f32(const float* x, int64_t count, unsigned long long* out, hipStream_t st) {
+  const int64_t blocks = (count + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(kchecksum, dim3((unsigned)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024)),
+                     dim3(kThreads), 0, st, x, count, out);
   return hipGetLastError();
 }
 
