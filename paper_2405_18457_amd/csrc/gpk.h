@@ -243,7 +243,7 @@ struct PcState {
   int rank;
   double dp;
 };
-constexpr int kMaxPrecondRank = 4096;  // padded rank limit (one inverse column in LDS)
+constexpr int kMaxPrecondRank = 8192;  // padded rank limit (one inverse column in LDS)
 int pc_parts(int64_t n);
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
 // One pivoted-Cholesky step j of k (column j for the current pivot, then the next
