@@ -15,8 +15,9 @@
 //                  FP64 MFMA, a tiled Cholesky (kchol), the triangular inverse
 //                  W = C^-1 by panelled forward substitution (one workgroup per
 //                  column) and M = W^T W on FP64 MFMA.
-//   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), both skinny
-//                  products LDS-tiled on FP64 MFMA with FP64 accumulation; the
+//   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), the skinny
+//                  products and M (L^T R) LDS-tiled on FP64 MFMA with FP64
+//                  accumulation; the
 //                  subtraction cancels most of R, which is why the arithmetic
 //                  is FP64.  The products read an FP32 copy of the factor (the
 //                  preconditioner is P = L~ L~^T + sigma^2 I for that copy L~,
@@ -209,9 +210,9 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
 constexpr int kTI = 32;  // rows i per LDS stage
 static_assert(kTI * 8 == 256, "B-tile loaders map 8 threads to each of the kTI rows");
 
-template <int NBT, int BMODE, typename TL>
+template <int NBT, int BMODE, typename TL, typename TR = float>
 __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
-                                              int64_t n, const float* __restrict__ R,
+                                              int64_t n, const TR* __restrict__ R,
                                               int64_t ldr, int nb, int64_t csize,
                                               double* __restrict__ part) {
   constexpr int NB = 16 * NBT;
@@ -345,17 +346,6 @@ __global__ __launch_bounds__(256) void kpc_trinv(const double* __restrict__ C, i
     __syncthreads();
   }
   for (int i = tid; i < kp; i += 256) W[(int64_t)a * kp + i] = y[i];
-}
-
-// S[a][b] = sum_t M[a][t] T[t][b], a < k, b < nb (M has leading dimension kp).
-__global__ void kpc_small(const double* __restrict__ M, int kp, const double* __restrict__ T,
-                          int k, int nb, double* __restrict__ S) {
-  const int64_t e = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
-  if (e >= (int64_t)k * nb) return;
-  const int a = (int)(e / nb), b = (int)(e % nb);
-  double v = 0.0;
-  for (int t = 0; t < k; ++t) v += M[(int64_t)a * kp + t] * T[(int64_t)t * nb + b];
-  S[e] = v;
 }
 
 // Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2 with L the FP32 factor
@@ -534,8 +524,11 @@ int64_t pc_inverse_parts(int kp) {
 }
 
 int64_t pc_apply_parts(int64_t n, int k, int c) {
-  const int64_t cs = chunk_rows(n, (k + 63) / 64 * ((c + 79) / 80), 2048);
-  return ((n + cs - 1) / cs) * (int64_t)k * c;
+  const int64_t tiles = (k + 63) / 64 * ((c + 79) / 80);
+  const int64_t cs = chunk_rows(n, tiles, 2048), cs2 = chunk_rows(k, tiles, 2048);
+  const int64_t nz1 = (n + cs - 1) / cs, nz2 = (k + cs2 - 1) / cs2;
+  const int64_t nz = nz1 > nz2 ? nz1 : nz2;
+  return nz * (int64_t)k * c;
 }
 
 hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
@@ -549,8 +542,13 @@ hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double*
                        c, cs, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz, k, c, T, c, 0, 0.0, 0);
-    hipLaunchKernelGGL(kpc_small, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, M, kp,
-                       T, k, c, S);
+    // S = M T (k x c, reduction over the k factor columns) on the same tiled product
+    const int64_t cs2 = chunk_rows(k, xt * yt, 2048);
+    const int64_t nz2 = (k + cs2 - 1) / cs2;
+    hipLaunchKernelGGL((kpc_tn<5, 0, double, double>), dim3(xt, yt, nz2), dim3(256), 0, st, M,
+                       (int64_t)kp, k, (int64_t)k, T, (int64_t)c, c, cs2, part);
+    hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
+                       (int)nz2, k, c, S, c, 0, 0.0, 0);
   }
   if (n > 0)
     hipLaunchKernelGGL((kpc_apply<5>), dim3((n + 63) / 64, (c + 79) / 80), dim3(256), 0, st, L,
