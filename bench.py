@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--init-centres", type=int, default=10)
     ap.add_argument("--init-steps", type=int, default=100)
     ap.add_argument("--init-m", type=int, default=10_000)
+    ap.add_argument("--init-single", type=int, default=10,
+                    help="single evaluations timed for the roofline of the heuristic line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler against a known traffic)")
@@ -176,15 +178,20 @@ def init_heuristic(args):
     idx = api.gp_nearest(ctx, inp["X"], int(centres[0]), m)
     api.gp_exact_mll(ctx, inp["X"], y, np.ones(d + 2), idx=idx)
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
     t0 = time.perf_counter()
     theta, each = api.gp_init_heuristic(ctx, inp["X"], y, centres, m, steps=args.init_steps,
                                         lr=0.1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    evals = len(centres) * args.init_steps
+    # the dominant kernels, timed live with HIP events on single evaluations (the
+    # heuristic itself runs its centroid subsets concurrently on separate streams)
+    ctx.profile_enable(True)
+    for _ in range(args.init_single):
+        api.gp_exact_mll(ctx, inp["X"], y, np.ones(d + 2), idx=idx)
+    torch.cuda.synchronize()
     prof = {k: ctx.profile_read(k) for k in (6, 7, 8)}
     ctx.profile_enable(False)
-    evals = len(centres) * args.init_steps
     fac_ms, fac_n = prof[7]
     # algorithmic FP64 work of one factorisation: Cholesky m^3/3, triangular inverse m^3/3,
     # H^-1 = W^T W (symmetric) m^3/3
@@ -203,9 +210,11 @@ def init_heuristic(args):
                                f"{args.init_steps} Adam steps (lr 0.1, softplus) from theta = 1",
                    "n": n, "d": d, "m": m, "centres": len(centres), "adam_steps": args.init_steps},
         "heuristic_s": round(wall, 3),
+        "heuristic_tflops": round(flops * evals / wall / 1e12, 3),  # m^3 per evaluation, wall clock
         "theta": [round(float(v), 6) for v in theta],
-        "kernel_ms": {"nearest": prof[6], "factor": prof[7], "finish": prof[8]},
-        "nearest_ms_per_call": round(prof[6][0] / max(prof[6][1], 1), 3),
+        "single_evaluation_ms": {"factor": round(fac_ms / max(fac_n, 1), 3),
+                                 "finish": round(prof[8][0] / max(prof[8][1], 1), 3),
+                                 "evaluations": fac_n},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,

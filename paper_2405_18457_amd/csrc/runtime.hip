@@ -1614,6 +1614,105 @@ void gp_init_cfg_default(gp_init_cfg* cfg) {
   cfg->theta0 = nullptr;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One centroid subset of the heuristic: its own workspace, streams, dependency
+// events and pinned staging, so the subsets' exact-likelihood evaluations run
+// concurrently (the leaves and small GEMMs of one evaluation leave most of the
+// chip idle).  Each lane issues exactly the kernels of the sequential path.
+constexpr int kHeurLanes = 16;                    // concurrent subsets at most
+constexpr int64_t kHeurLaneMemory = 64ll << 30;   // and their workspaces within 64 GiB
+
+struct HeurLane {
+  ExactWs ws{};
+  int64_t* idx = nullptr;
+  hipStream_t st = nullptr, side = nullptr;
+  std::vector<hipEvent_t> ev;
+  double* pin = nullptr;  // [0, kMaxD): 1/ell; [kMaxD, 2 kMaxD + 4): results; then status
+  std::vector<void*> mem;
+  std::vector<double> nu, mom, vel, th, g;
+  int64_t step = 0;
+};
+
+struct LaneSet {
+  std::vector<HeurLane> lanes;
+  ~LaneSet() {
+    for (auto& l : lanes) {
+      if (l.st) (void)hipStreamSynchronize(l.st);
+      if (l.side) (void)hipStreamSynchronize(l.side);
+      for (auto e : l.ev) (void)hipEventDestroy(e);
+      if (l.side) (void)hipStreamDestroy(l.side);
+      if (l.st) (void)hipStreamDestroy(l.st);
+      for (auto q : l.mem) (void)hipFree(q);
+      if (l.pin) (void)hipHostFree(l.pin);
+    }
+  }
+};
+
+int64_t lane_bytes(int64_t m, int d) {
+  const int64_t mp = round_up(m, kExactTile);
+  return 8 * (2 * mp * mp + mp * (d + 5) + exact_part_doubles(mp) + exact_gpart_doubles(mp, d) +
+              2 * kMaxD + 4) + 8 * m + 4096;
+}
+
+int lane_alloc(gp_ctx* ctx, HeurLane& l, int64_t m, int d) {
+  auto dev = [&](size_t bytes, void** out) -> int {
+    if (hipMalloc(out, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, GP_ERR_NO_WORKSPACE, "hipMalloc of %zu bytes for a heuristic lane failed",
+                  bytes);
+    }
+    l.mem.push_back(*out);
+    return GP_OK;
+  };
+  ExactWs& w = l.ws;
+  w.m = m;
+  w.d = d;
+  w.mp = round_up(m, kExactTile);
+  const size_t mp = (size_t)w.mp;
+  CHK(dev(mp * mp * 8, (void**)&w.A));
+  CHK(dev(mp * mp * 8, (void**)&w.W));
+  CHK(dev(mp * d * 8, (void**)&w.xs));
+  CHK(dev(mp * 8, (void**)&w.ys));
+  CHK(dev(mp * 8, (void**)&w.diag));
+  CHK(dev(mp * 8, (void**)&w.v));
+  CHK(dev(mp * 8, (void**)&w.alpha));
+  CHK(dev((size_t)exact_part_doubles(w.mp) * 8, (void**)&w.part));
+  CHK(dev((size_t)exact_gpart_doubles(w.mp, d) * 8, (void**)&w.gpart));
+  CHK(dev(((size_t)kMaxD + 4) * 8, (void**)&w.out));
+  CHK(dev((size_t)kMaxD * 8, (void**)&w.inv_ell));
+  CHK(dev(sizeof(int), (void**)&w.status));
+  CHK(dev((size_t)m * 8, (void**)&l.idx));
+  HIPCHK(hipHostMalloc((void**)&l.pin, (2 * kMaxD + 16) * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&l.side, hipStreamNonBlocking));
+  l.ev.resize(exact_events(w.mp), nullptr);
+  for (auto& e : l.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return GP_OK;
+}
+
+// Enqueue one evaluation of lane l at its current theta (results land in l.pin).
+int lane_issue(gp_ctx* ctx, HeurLane& l) {
+  const ExactWs& w = l.ws;
+  const int d = w.d;
+  for (int k = 0; k < d; ++k) l.pin[k] = 1.0 / l.th[k];
+  HIPCHK(hipMemcpyAsync(w.inv_ell, l.pin, d * sizeof(double), hipMemcpyHostToDevice, l.st));
+  HIPCHK(exact_factor(w.xs, d, w.m, w.mp, w.inv_ell, l.th[d], l.th[d + 1], w.A, w.W, w.diag,
+                      w.status, l.st, l.side, l.ev.data(), (int)l.ev.size()));
+  HIPCHK(exact_finish(w.xs, w.ys, d, w.m, w.mp, w.inv_ell, l.th[d], l.th[d + 1], w.A, w.W, w.diag,
+                      w.v, w.alpha, w.part, w.gpart, w.out, l.st));
+  HIPCHK(hipMemcpyAsync(l.pin + kMaxD, w.out, (d + 4) * sizeof(double), hipMemcpyDeviceToHost,
+                        l.st));
+  HIPCHK(hipMemcpyAsync(l.pin + 2 * kMaxD + 8, w.status, sizeof(int), hipMemcpyDeviceToHost, l.st));
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
                       const int64_t* centres, int nc, int64_t m, const gp_init_cfg* cfg_in,
                       double* theta_out, double* theta_each) {
@@ -1638,35 +1737,68 @@ int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float
   CHK(check_mat(ctx, "y", y, n, 1, 1));
   HIPCHK(hipSetDevice(ctx->device));
   const int p = d + 2;
-  int64_t* idx;
-  CHK(ensure(ctx, B_NRIDX, (size_t)m, &idx));
-  std::vector<double> nu(p), mom(p), vel(p), th(p), g(p), sum(p, 0.0);
+  // concurrent lanes: at most kHeurLanes, and within kHeurLaneMemory of device memory
+  const int64_t per = lane_bytes(m, d);
+  const int group = (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)nc, (int64_t)kHeurLanes, kHeurLaneMemory / per}));
+  std::vector<double> sum(p, 0.0);
   Progress pr;
-  for (int c = 0; c < nc; ++c) {
-    CHK(nearest_run(ctx, X, n, d, centres[c], m, idx));
-    ExactWs ws;
-    CHK(exact_prepare(ctx, X, n, d, y, idx, m, ws));
-    for (int k = 0; k < p; ++k) {
-      const double t0 = cfg.theta0 ? cfg.theta0[k] : 1.0;
-      nu[k] = cfg.transform == GP_LOG ? std::log(t0) : t0 + std::log(-std::expm1(-t0));
-      mom[k] = vel[k] = 0.0;
+  for (int c0 = 0; c0 < nc; c0 += group) {
+    const int cn = std::min(group, nc - c0);
+    LaneSet set;
+    set.lanes.resize(cn);
+    for (int q = 0; q < cn; ++q) {
+      HeurLane& l = set.lanes[q];
+      CHK(lane_alloc(ctx, l, m, d));
+      // steps 1-2 on the context's stream: nearest rows, gathered subset
+      CHK(nearest_run(ctx, X, n, d, centres[c0 + q], m, l.idx));
+      HIPCHK(hipMemsetAsync(l.ws.status, 0, sizeof(int), ctx->stream));
+      HIPCHK(exact_gather(X, n, d, l.idx, m, l.ws.mp, y, l.ws.xs, l.ws.ys, l.ws.status,
+                          ctx->stream));
+      l.nu.resize(p);
+      l.mom.assign(p, 0.0);
+      l.vel.assign(p, 0.0);
+      l.th.resize(p);
+      l.g.resize(p);
+      for (int k = 0; k < p; ++k) {
+        const double t0 = cfg.theta0 ? cfg.theta0[k] : 1.0;
+        l.nu[k] = cfg.transform == GP_LOG ? std::log(t0) : t0 + std::log(-std::expm1(-t0));
+      }
     }
-    int64_t step = 0;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // step 3: Adam on the exact likelihood, all lanes of the group in lockstep
     for (int it = 0; it < cfg.steps; ++it) {
-      gp_nu_to_theta(p, nu.data(), cfg.transform, th.data());
-      CHK(exact_run(ctx, ws, th.data(), nullptr, g.data()));
-      gp_adam_ascent(p, nu.data(), mom.data(), vel.data(), &step, g.data(), cfg.lr,
-                     cfg.transform);
+      for (auto& l : set.lanes) {
+        gp_nu_to_theta(p, l.nu.data(), cfg.transform, l.th.data());
+        CHK(lane_issue(ctx, l));
+      }
+      for (int q = 0; q < cn; ++q) {
+        HeurLane& l = set.lanes[q];
+        HIPCHK(hipStreamSynchronize(l.st));
+        int stv;
+        std::memcpy(&stv, l.pin + 2 * kMaxD + 8, sizeof(int));
+        if (stv & 1) return fail(ctx, GP_ERR_INVALID_ARG, "a row index lies outside [0, n)");
+        if (stv & 2)
+          return fail(ctx, GP_ERR_BREAKDOWN,
+                      "non-positive pivot in the Cholesky factorisation of H (centre %d)",
+                      c0 + q);
+        for (int k = 0; k < p; ++k) l.g[k] = l.pin[kMaxD + 2 + k];
+        gp_adam_ascent(p, l.nu.data(), l.mom.data(), l.vel.data(), &l.step, l.g.data(), cfg.lr,
+                       cfg.transform);
+      }
     }
-    gp_nu_to_theta(p, nu.data(), cfg.transform, th.data());
-    for (int k = 0; k < p; ++k) {
-      if (!std::isfinite(th[k]) || !(th[k] > 0.0))
-        return fail(ctx, GP_ERR_NONFINITE, "theta[%d] = %g after the maximisation for centre %d",
-                    k, th[k], c);
-      sum[k] += th[k];
-      if (theta_each) theta_each[(int64_t)c * p + k] = th[k];
+    for (int q = 0; q < cn; ++q) {
+      HeurLane& l = set.lanes[q];
+      gp_nu_to_theta(p, l.nu.data(), cfg.transform, l.th.data());
+      for (int k = 0; k < p; ++k) {
+        if (!std::isfinite(l.th[k]) || !(l.th[k] > 0.0))
+          return fail(ctx, GP_ERR_NONFINITE,
+                      "theta[%d] = %g after the maximisation for centre %d", k, l.th[k], c0 + q);
+        sum[k] += l.th[k];
+        if (theta_each) theta_each[(int64_t)(c0 + q) * p + k] = l.th[k];
+      }
     }
-    pr.count("init heuristic: centres done", c + 1, nc);
+    pr.count("init heuristic: centres done", c0 + cn, nc);
   }
   for (int k = 0; k < p; ++k) theta_out[k] = sum[k] / nc;
   return GP_OK;

@@ -211,3 +211,17 @@ def test_init_heuristic_theta0_log_transform_and_errors(ctx):
                dict(centres=[0], m=10, lr=0.0), dict(centres=[0], m=10, steps=-1)):
         with pytest.raises(api.GPError):
             api.gp_init_heuristic(ctx, Xd, yd, **kw)
+
+
+def test_init_heuristic_more_centres_than_concurrent_lanes(ctx):
+    # 18 centroid rows: the library runs at most 16 subsets concurrently, so this
+    # takes two groups; every per-centroid result must still match the oracle.
+    w = wl.WORKLOADS["D"]
+    X = wl.draw_inputs(w, n=2000)
+    y = _targets(X * 6.0, 11, noise=0.05)
+    centres = wl.draw_centroids(w, count=18, n=2000)
+    announce("init heuristic 18 centres")
+    mean, each = api.gp_init_heuristic(ctx, dev(X), dev(y), centres, m=100, steps=4, lr=0.1)
+    rmean, reach = ih.init_heuristic(X, y, centres, m=100, steps=4, lr=0.1)
+    np.testing.assert_allclose(each, reach, rtol=1e-7)
+    np.testing.assert_allclose(mean, rmean, rtol=1e-7)
