@@ -228,15 +228,24 @@ __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t 
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // loader coordinates: 4 threads per 32-float row segment, 8 floats each
+  // loader coordinates: 4 threads per 32-float row segment, 8 floats each (two
+  // 16-byte loads when the segment is whole: rows start at multiples of 64 floats
+  // and chunks at multiples of 16 rows)
   const int lr = tid >> 2, lc = (tid & 3) * 8;
   for (int64_t i = i0; i < i1; i += kTI) {
     {
       const int a = a0 + lr;
+      if (sizeof(TL) == 4 && a < ka && i + lc + 8 <= i1) {
+        const float4* q = reinterpret_cast<const float4*>(L + (int64_t)a * ldl + i + lc);
+        const float4 u0 = q[0], u1 = q[1];
+        As[lr][lc + 0] = u0.x; As[lr][lc + 1] = u0.y; As[lr][lc + 2] = u0.z; As[lr][lc + 3] = u0.w;
+        As[lr][lc + 4] = u1.x; As[lr][lc + 5] = u1.y; As[lr][lc + 6] = u1.z; As[lr][lc + 7] = u1.w;
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t ii = i + lc + e;
-        As[lr][lc + e] = (a < ka && ii < i1) ? (double)L[(int64_t)a * ldl + ii] : 0.0;
+        for (int e = 0; e < 8; ++e) {
+          const int64_t ii = i + lc + e;
+          As[lr][lc + e] = (a < ka && ii < i1) ? (double)L[(int64_t)a * ldl + ii] : 0.0;
+        }
       }
     }
     if (BMODE == 0) {
@@ -252,10 +261,17 @@ __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t 
     } else {
       for (int rr = lr; rr < NB; rr += 64) {
         const int bcol = b0 + rr;
+        if (sizeof(TL) == 4 && bcol < nb && i + lc + 8 <= i1) {
+          const float4* q = reinterpret_cast<const float4*>(L + (int64_t)bcol * ldl + i + lc);
+          const float4 u0 = q[0], u1 = q[1];
+          Bs[lc + 0][rr] = u0.x; Bs[lc + 1][rr] = u0.y; Bs[lc + 2][rr] = u0.z; Bs[lc + 3][rr] = u0.w;
+          Bs[lc + 4][rr] = u1.x; Bs[lc + 5][rr] = u1.y; Bs[lc + 6][rr] = u1.z; Bs[lc + 7][rr] = u1.w;
+        } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t ii = i + lc + e;
-          Bs[lc + e][rr] = (bcol < nb && ii < i1) ? (double)L[(int64_t)bcol * ldl + ii] : 0.0;
+          for (int e = 0; e < 8; ++e) {
+            const int64_t ii = i + lc + e;
+            Bs[lc + e][rr] = (bcol < nb && ii < i1) ? (double)L[(int64_t)bcol * ldl + ii] : 0.0;
+          }
         }
       }
     }
@@ -369,15 +385,23 @@ __global__ __launch_bounds__(256) void kpc_apply(const float* __restrict__ L, in
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // loader: 8 threads per 64-float row segment of the factor, 8 floats each
+  // loader: 8 threads per 64-float row segment of the factor, 8 floats each (two
+  // 16-byte loads when the segment is whole)
   const int lr = tid >> 3, lc = (tid & 7) * 8;
   for (int t0 = 0; t0 < k; t0 += kTI) {
     {
       const int t = t0 + lr;
+      if (t < k && i0 + lc + 8 <= n) {
+        const float4* q = reinterpret_cast<const float4*>(L + (int64_t)t * ldl + i0 + lc);
+        const float4 u0 = q[0], u1 = q[1];
+        As[lr][lc + 0] = u0.x; As[lr][lc + 1] = u0.y; As[lr][lc + 2] = u0.z; As[lr][lc + 3] = u0.w;
+        As[lr][lc + 4] = u1.x; As[lr][lc + 5] = u1.y; As[lr][lc + 6] = u1.z; As[lr][lc + 7] = u1.w;
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t ii = i0 + lc + e;
-        As[lr][lc + e] = (t < k && ii < n) ? (double)L[(int64_t)t * ldl + ii] : 0.0;
+        for (int e = 0; e < 8; ++e) {
+          const int64_t ii = i0 + lc + e;
+          As[lr][lc + e] = (t < k && ii < n) ? (double)L[(int64_t)t * ldl + ii] : 0.0;
+        }
       }
     }
     {
