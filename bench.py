@@ -435,6 +435,15 @@ def main():
     }
     if args.form == "bf16x3+adjoint":
         rec["roofline"] = roofline(n, d, s + 1, prof)
+    # the FP32 fused product (the true-residual products of every step) on its own peak
+    f32_ms, f32_n = prof[4]
+    if f32_n:
+        t = f32_ms / f32_n / 1e3
+        tf = 2.0 * (s + 1) * float(n) * n / t / 1e12
+        rec["fp32_product_mfma"] = {"kernel": "kfwd_f32_xt<CT=5, RS=4>",
+                                    "avg_launch_ms": round(t * 1e3, 3), "launches": f32_n,
+                                    "achieved": round(tf, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(tf / FP32_MFMA_PEAK_TFLOPS, 4)}
     rec["kernel_ms"] = {"fwd_bf16": prof[0], "adjoint": prof[1], "rff": prof[2], "cg_vec": prof[3],
                         "fwd_fp32": prof[4], "precond": prof[5]}
     if args.compare:
