@@ -206,16 +206,39 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
 // LDS as FP64 and every wave runs v_mfma_f64_16x16x4f64 on 16 a-rows x NBT
 // column tiles (A lane: L[a0 + 16w + l%16][i + 4s + l/16]; B lane:
 // Bop(i + 4s + l/16, b0 + 16u + l%16); D lane q: (a0 + 16w + 4q + l/16,
-// b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.
+// b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.  WPE is the
+// occupancy the register allocation aims for (4 waves per SIMD is also the LDS
+// limit; the all-FP64 instantiation needs 3 to stay clear of spills).
 constexpr int kTI = 32;  // rows i per LDS stage
 static_assert(kTI * 8 == 256, "B-tile loaders map 8 threads to each of the kTI rows");
 
-template <int NBT, int BMODE, typename TL, typename TR = float>
-__global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
+// Eight consecutive entries [i, i + 8) of row a of a [rows][ldl] operand, zero
+// past iend or the row count; two 16-byte loads when the segment is whole (FP32
+// rows start at multiples of 64 values and every segment at a multiple of 8).
+template <typename T>
+__device__ __forceinline__ void load_seg(const T* __restrict__ L, int rows, int64_t ldl, int a,
+                                         int64_t i, int64_t iend, T (&v)[8]) {
+  if constexpr (sizeof(T) == 4) {
+    if (a < rows && i + 8 <= iend) {
+      const float4* q = reinterpret_cast<const float4*>(L + (int64_t)a * ldl + i);
+      const float4 u0 = q[0], u1 = q[1];
+      v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+      v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    v[e] = (a < rows && i + e < iend) ? L[(int64_t)a * ldl + i + e] : T(0);
+}
+
+template <int NBT, int BMODE, typename TL, typename TR = float, int WPE = 4>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
                                               int64_t n, const TR* __restrict__ R,
                                               int64_t ldr, int nb, int64_t csize,
                                               double* __restrict__ part) {
   constexpr int NB = 16 * NBT;
+  static_assert(BMODE == 0 || NB == 64, "the factor-operand loader covers 64 columns");
   __shared__ double As[64][kTI + 1];
   __shared__ double Bs[kTI][NB + 1];
   const int tid = threadIdx.x;
@@ -228,54 +251,42 @@ __global__ __launch_bounds__(256) void kpc_tn(const TL* __restrict__ L, int64_t 
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // loader coordinates: 4 threads per 32-float row segment, 8 floats each (two
-  // 16-byte loads when the segment is whole: rows start at multiples of 64 floats
-  // and chunks at multiples of 16 rows)
+  // loaders: the factor tile with 4 threads per 32-value row segment (8 values
+  // each); BMODE 0 with 8 threads per row of the B tile, NB / 8 consecutive
+  // columns each; BMODE 1 like the factor tile.  The next stage is fetched into
+  // registers while the MFMAs of the current one run.
   const int lr = tid >> 2, lc = (tid & 3) * 8;
-  for (int64_t i = i0; i < i1; i += kTI) {
-    {
-      const int a = a0 + lr;
-      if (sizeof(TL) == 4 && a < ka && i + lc + 8 <= i1) {
-        const float4* q = reinterpret_cast<const float4*>(L + (int64_t)a * ldl + i + lc);
-        const float4 u0 = q[0], u1 = q[1];
-        As[lr][lc + 0] = u0.x; As[lr][lc + 1] = u0.y; As[lr][lc + 2] = u0.z; As[lr][lc + 3] = u0.w;
-        As[lr][lc + 4] = u1.x; As[lr][lc + 5] = u1.y; As[lr][lc + 6] = u1.z; As[lr][lc + 7] = u1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t ii = i + lc + e;
-          As[lr][lc + e] = (a < ka && ii < i1) ? (double)L[(int64_t)a * ldl + ii] : 0.0;
-        }
-      }
-    }
-    if (BMODE == 0) {
-      // 8 threads per row of the tile, NB / 8 consecutive columns each
-      constexpr int BPT = NB / 8;
-      const int r = tid >> 3, cb = (tid & 7) * BPT;
-      const int64_t ii = i + r;
+  constexpr int BPT = NB / 8;
+  const int br = tid >> 3, bc = (tid & 7) * BPT;
+  TL ra[8];
+  TR rb[BMODE == 0 ? BPT : 1];
+  TL rl[8];
+  auto fetch = [&](int64_t i) {
+    load_seg(L, ka, ldl, a0 + lr, i + lc, i1, ra);
+    if constexpr (BMODE == 0) {
+      const int64_t ii = i + br;
 #pragma unroll
       for (int e = 0; e < BPT; ++e) {
-        const int bcol = b0 + cb + e;
-        Bs[r][cb + e] = (ii < i1 && bcol < nb) ? (double)R[ii * ldr + bcol] : 0.0;
+        const int bcol = b0 + bc + e;
+        rb[e] = (ii < i1 && bcol < nb) ? R[ii * ldr + bcol] : TR(0);
       }
     } else {
-      for (int rr = lr; rr < NB; rr += 64) {
-        const int bcol = b0 + rr;
-        if (sizeof(TL) == 4 && bcol < nb && i + lc + 8 <= i1) {
-          const float4* q = reinterpret_cast<const float4*>(L + (int64_t)bcol * ldl + i + lc);
-          const float4 u0 = q[0], u1 = q[1];
-          Bs[lc + 0][rr] = u0.x; Bs[lc + 1][rr] = u0.y; Bs[lc + 2][rr] = u0.z; Bs[lc + 3][rr] = u0.w;
-          Bs[lc + 4][rr] = u1.x; Bs[lc + 5][rr] = u1.y; Bs[lc + 6][rr] = u1.z; Bs[lc + 7][rr] = u1.w;
-        } else {
+      load_seg(L, nb, ldl, b0 + lr, i + lc, i1, rl);
+    }
+  };
+  if (i0 < i1) fetch(i0);
+  for (int64_t i = i0; i < i1; i += kTI) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int64_t ii = i + lc + e;
-            Bs[lc + e][rr] = (bcol < nb && ii < i1) ? (double)L[(int64_t)bcol * ldl + ii] : 0.0;
-          }
-        }
-      }
+    for (int e = 0; e < 8; ++e) As[lr][lc + e] = (double)ra[e];
+    if constexpr (BMODE == 0) {
+#pragma unroll
+      for (int e = 0; e < BPT; ++e) Bs[br][bc + e] = (double)rb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[lc + e][lr] = (double)rl[e];
     }
     __syncthreads();
+    if (i + kTI < i1) fetch(i + kTI);
 #pragma unroll
     for (int s4 = 0; s4 < kTI / 4; ++s4) {
       const double av = As[16 * wave + la][4 * s4 + lk];
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(256) void kpc_trinv(const double* __restrict__ C, i
 // S[t + 4s + l/16][c0 + 16u + l%16]; D lane q: (i0 + 16w + 4q + l/16,
 // c0 + 16u + l%16)).
 template <int NBT>
-__global__ __launch_bounds__(256) void kpc_apply(const float* __restrict__ L, int64_t ldl, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kpc_apply(const float* __restrict__ L, int64_t ldl, int k,
                                                  int64_t n, const double* __restrict__ S, int nb,
                                                  const float* __restrict__ R, int64_t ldr,
                                                  float* __restrict__ Z, int64_t ldz, double s2) {
@@ -385,36 +396,31 @@ __global__ __launch_bounds__(256) void kpc_apply(const float* __restrict__ L, in
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // loader: 8 threads per 64-float row segment of the factor, 8 floats each (two
-  // 16-byte loads when the segment is whole)
+  // loaders: 8 threads per 64-value row segment of the factor (8 values each) and
+  // 8 threads per row of the S tile (NB / 8 columns each); the next stage is
+  // fetched into registers while the MFMAs of the current one run.
   const int lr = tid >> 3, lc = (tid & 7) * 8;
+  constexpr int BPT = NB / 8;
+  const int bc = (tid & 7) * BPT;
+  float ra[8];
+  double rb[BPT];
+  auto fetch = [&](int t0) {
+    load_seg(L, k, ldl, t0 + lr, i0 + lc, n, ra);
+    const int t = t0 + lr;
+#pragma unroll
+    for (int e = 0; e < BPT; ++e) {
+      const int col = c0 + bc + e;
+      rb[e] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
+    }
+  };
+  if (k > 0) fetch(0);
   for (int t0 = 0; t0 < k; t0 += kTI) {
-    {
-      const int t = t0 + lr;
-      if (t < k && i0 + lc + 8 <= n) {
-        const float4* q = reinterpret_cast<const float4*>(L + (int64_t)t * ldl + i0 + lc);
-        const float4 u0 = q[0], u1 = q[1];
-        As[lr][lc + 0] = u0.x; As[lr][lc + 1] = u0.y; As[lr][lc + 2] = u0.z; As[lr][lc + 3] = u0.w;
-        As[lr][lc + 4] = u1.x; As[lr][lc + 5] = u1.y; As[lr][lc + 6] = u1.z; As[lr][lc + 7] = u1.w;
-      } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t ii = i0 + lc + e;
-          As[lr][lc + e] = (t < k && ii < n) ? (double)L[(int64_t)t * ldl + ii] : 0.0;
-        }
-      }
-    }
-    {
-      constexpr int BPT = NB / 8;  // 8 threads per row of the tile
-      const int r = tid >> 3, cb = (tid & 7) * BPT;
-      const int t = t0 + r;
+    for (int e = 0; e < 8; ++e) As[lr][lc + e] = (double)ra[e];
 #pragma unroll
-      for (int e = 0; e < BPT; ++e) {
-        const int col = c0 + cb + e;
-        Bs[r][cb + e] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
-      }
-    }
+    for (int e = 0; e < BPT; ++e) Bs[lr][bc + e] = rb[e];
     __syncthreads();
+    if (t0 + kTI < k) fetch(t0 + kTI);
 #pragma unroll
     for (int s4 = 0; s4 < kTI / 4; ++s4) {
       const double av = As[4 * s4 + lk][16 * wave + la];
@@ -569,7 +575,7 @@ hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double*
     // S = M T (k x c, reduction over the k factor columns) on the same tiled product
     const int64_t cs2 = chunk_rows(k, xt * yt, 2048);
     const int64_t nz2 = (k + cs2 - 1) / cs2;
-    hipLaunchKernelGGL((kpc_tn<5, 0, double, double>), dim3(xt, yt, nz2), dim3(256), 0, st, M,
+    hipLaunchKernelGGL((kpc_tn<5, 0, double, double, 3>), dim3(xt, yt, nz2), dim3(256), 0, st, M,
                        (int64_t)kp, k, (int64_t)k, T, (int64_t)c, c, cs2, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz2, k, c, S, c, 0, 0.0, 0);
