@@ -29,9 +29,9 @@ Processes", NeurIPS 2024) in float64, slow and obvious:
               centroid average (App. B "Iterative Optimiser").
 
 Parity status: every function has at least one independent pin in
-``tests/test_oracle_pins.py`` except the alternating-projections block
-*selection order* (any argmax rule gives a valid AP; the paper's code is not
-available), which is marked "parity unpinned" in ``solvers.ap``.
+``tests/test_oracle_pins.py``, ``tests/test_oracle_precond.py`` or
+``tests/test_oracle_init.py``; the alternating-projections block selection is
+pinned as the literal reading of its printed score (a hand-computed case).
 """
 from . import kernel, mll, rff, solvers, optim, train, precond, init_heuristic  # noqa: F401
 

@@ -151,9 +151,9 @@ def ap(op, B, block=1000, tol=0.01, max_epochs=None, U0=None):
     rows.  Every block's Cholesky factor is computed once per call (once per
     marginal-likelihood step) and cached.  The block chosen each iteration
     maximises || r_y[I] + sum_j r_j[I] || (the printed score, read literally);
-    ties go to the lowest block index.  Parity unpinned for the selection
-    order against the paper's own code (any argmax rule is a valid AP); the
-    solver itself is pinned by exactness and convergence properties.
+    ties go to the lowest block index.  The selection rule is pinned by a
+    hand-computed case in which this score and a per-column score choose
+    different blocks; the solver itself by exactness and convergence properties.
     """
     Bt, V, scale = _normalise(B, U0)
     n = Bt.shape[0]

@@ -395,6 +395,37 @@ def test_ap_projection_zeroes_selected_block_and_converges():
     assert st["iterations"] == 5
 
 
+class _IdentityOperator:
+    def __init__(self, n):
+        self.H = np.eye(n)
+
+    def matvec(self, V):
+        return self.H @ V
+
+    def rows(self, idx):
+        return self.H[idx, :]
+
+    def block(self, idx):
+        return self.H[np.ix_(idx, idx)]
+
+
+def test_ap_selects_by_the_norm_of_the_summed_residual_block():
+    # H = I, two blocks of two rows.  In block 0 the two residual columns cancel
+    # in their sum, so the summed-residual score picks block 1 first although
+    # each column alone is larger in block 0 (a per-column score would pick block
+    # 0).  Block 1's projection zeroes it, leaving a tie at zero, which goes to
+    # the lower index; with H = I the two projections solve the system exactly.
+    B = np.array([[1.0, -1.0], [0.0, 0.0], [0.3, 0.3], [0.0, 0.0]])
+    U, st = solvers.ap(_IdentityOperator(4), B, block=2, tol=1e-12)
+    assert st["chosen"] == [1, 0]
+    assert st["iterations"] == 2 and st["converged"]
+    np.testing.assert_allclose(U, B, rtol=1e-15, atol=1e-15)
+    # the per-column reading would differ on the first choice
+    Bt = B / np.linalg.norm(B, axis=0)
+    per_column = [np.abs(Bt[I]).sum() for I in (np.arange(2), np.arange(2, 4))]
+    assert int(np.argmax(per_column)) == 0
+
+
 def test_sgd_full_batch_is_heavy_ball_and_converges():
     X, theta, B = _spd_problem(n=30, sigma=0.6)
     op = solvers.DenseOperator(X, theta)
