@@ -72,3 +72,20 @@ def test_init_cfg_default_is_the_small_data_setting():
     N.lib().gp_init_cfg_default(C.byref(cfg))
     assert cfg.steps == 100 and cfg.lr == 0.1 and cfg.transform == N.GP_SOFTPLUS
     assert not cfg.theta0
+
+
+def test_no_gpu_means_an_error_not_a_fallback():
+    # Without a visible GPU the library reports GP_ERR_HIP from context creation
+    # and hands out no context: nothing downstream can run on the host instead.
+    import ctypes as C
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    L = N.lib()
+    h = C.c_void_p(1)
+    assert L.gp_ctx_create(0, None, C.byref(h)) == N.GP_ERR_HIP
+    assert h.value is None
+    assert L.gp_ctx_create(0, None, None) == N.GP_ERR_INVALID_ARG
+    from paper_2405_18457_amd import api
+    with pytest.raises(Exception):
+        api.Context(0)
