@@ -507,6 +507,48 @@ def test_trainer_exact_solver_ascends_mll():
     assert last > first
 
 
+def _torch_surrogate_grad(nu, X, y, Z, transform):
+    """Gradient in nu of a torch-autograd surrogate whose theta-gradient is the
+    standard estimator with exact solves: -y^T H^-1 y / 2 gives alpha^T dH alpha / 2,
+    and -(1/2s) sum_j v_j^T H z_j with v_j = H^-1 z_j held constant gives the
+    probe term.  The Matern-3/2 kernel is written here independently."""
+    n, d = X.shape
+    s = Z.shape[1]
+    p = torch.tensor(nu, dtype=torch.float64, requires_grad=True)
+    th = torch.exp(p) if transform == "log" else torch.nn.functional.softplus(p)
+    Xs = torch.tensor(X) / th[:d]
+    r2 = ((Xs[:, None, :] - Xs[None, :, :]) ** 2).sum(-1)
+    eye = torch.eye(n, dtype=torch.bool)
+    r = torch.sqrt(torch.where(eye, torch.ones_like(r2), r2)) * 3.0 ** 0.5
+    K = torch.where(eye, th[d] ** 2 * torch.ones_like(r2), th[d] ** 2 * (1 + r) * torch.exp(-r))
+    H = K + th[d + 1] ** 2 * torch.eye(n, dtype=torch.float64)
+    yt, Zt = torch.tensor(y), torch.tensor(Z)
+    V = torch.linalg.solve(H.detach(), Zt)
+    surrogate = -0.5 * yt @ torch.linalg.solve(H, yt) - (V * (H @ Zt)).sum() / (2 * s)
+    surrogate.backward()
+    return p.grad.numpy()
+
+
+@pytest.mark.parametrize("transform", ["log", "softplus"])
+def test_trainer_trajectory_matches_torch_autograd_and_adam(transform):
+    # the whole composition (right-hand side, exact solve, estimator weights,
+    # chain rule through the transform, Adam ascent) against torch autograd of
+    # the surrogate and torch.optim.Adam(maximize=True)
+    X, y, _ = _small_problem(31, n=35)
+    Z = np.random.default_rng(32).standard_normal((35, 6))
+    theta0 = np.array([0.9, 1.4, 1.1, 0.6])
+    tr = train.Trainer(X, y, theta0, "standard", {"Z": Z}, lr=0.05, transform=transform,
+                       solver="exact")
+    p = torch.tensor(optim.to_nu(theta0, transform), dtype=torch.float64)
+    opt = torch.optim.Adam([p], lr=0.05, maximize=True)
+    for _ in range(6):
+        theta, _, _ = tr.step()
+        p.grad = torch.tensor(_torch_surrogate_grad(p.detach().numpy(), X, y, Z, transform))
+        opt.step()
+        np.testing.assert_allclose(tr.nu, p.detach().numpy(), rtol=1e-9, atol=1e-12)
+    assert not np.allclose(tr.nu, optim.to_nu(theta0, transform))
+
+
 def test_workload_generators_are_deterministic_and_shaped():
     w = wl.WORKLOADS["D"]
     X = wl.draw_inputs(w, n=1000)
