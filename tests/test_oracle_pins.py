@@ -549,6 +549,52 @@ def test_trainer_trajectory_matches_torch_autograd_and_adam(transform):
     assert not np.allclose(tr.nu, optim.to_nu(theta0, transform))
 
 
+def _torch_pathwise_surrogate_grad(nu, X, y, t, W, w_eps, transform):
+    """As above for the pathwise estimator: xi = phi(x) W + sigma w_eps from the
+    current theta (held constant), zhat = H^-1 xi held constant, and the probe
+    term -(1/2s) sum_j zhat_j^T H zhat_j; features written here independently."""
+    n, d = X.shape
+    s = W.shape[1]
+    p = torch.tensor(nu, dtype=torch.float64, requires_grad=True)
+    th = torch.exp(p) if transform == "log" else torch.nn.functional.softplus(p)
+    Xt = torch.tensor(X)
+    Xs = Xt / th[:d]
+    r2 = ((Xs[:, None, :] - Xs[None, :, :]) ** 2).sum(-1)
+    eye = torch.eye(n, dtype=torch.bool)
+    r = torch.sqrt(torch.where(eye, torch.ones_like(r2), r2)) * 3.0 ** 0.5
+    K = torch.where(eye, th[d] ** 2 * torch.ones_like(r2), th[d] ** 2 * (1 + r) * torch.exp(-r))
+    H = K + th[d + 1] ** 2 * torch.eye(n, dtype=torch.float64)
+    with torch.no_grad():
+        phase = Xt @ (torch.tensor(t) / th[:d]).T
+        M = phase.shape[1]
+        feats = th[d] / M ** 0.5 * torch.cat([torch.cos(phase), torch.sin(phase)], dim=1)
+        xi = feats @ torch.tensor(W) + th[d + 1] * torch.tensor(w_eps)
+        zhat = torch.linalg.solve(H, xi)
+    yt = torch.tensor(y)
+    surrogate = -0.5 * yt @ torch.linalg.solve(H, yt) - (zhat * (H @ zhat)).sum() / (2 * s)
+    surrogate.backward()
+    return p.grad.numpy()
+
+
+def test_pathwise_trainer_trajectory_matches_torch_autograd_and_adam():
+    X, y, _ = _small_problem(33, n=35)
+    g = np.random.default_rng(34)
+    M, s = 40, 5
+    t = g.standard_normal((M, 2)) * np.sqrt(3.0 / g.chisquare(3, (M, 1)))
+    W, w_eps = g.standard_normal((2 * M, s)), g.standard_normal((35, s))
+    theta0 = np.array([1.2, 0.8, 1.0, 0.4])
+    tr = train.Trainer(X, y, theta0, "pathwise", {"t": t, "W": W, "w_eps": w_eps}, lr=0.05,
+                       solver="exact")
+    p = torch.tensor(optim.to_nu(theta0, "softplus"), dtype=torch.float64)
+    opt = torch.optim.Adam([p], lr=0.05, maximize=True)
+    for _ in range(6):
+        tr.step()
+        p.grad = torch.tensor(_torch_pathwise_surrogate_grad(p.detach().numpy(), X, y, t, W,
+                                                             w_eps, "softplus"))
+        opt.step()
+        np.testing.assert_allclose(tr.nu, p.detach().numpy(), rtol=1e-9, atol=1e-12)
+
+
 def test_workload_generators_are_deterministic_and_shaped():
     w = wl.WORKLOADS["D"]
     X = wl.draw_inputs(w, n=1000)
