@@ -160,8 +160,9 @@ typedef struct gp_solver_cfg {
                            recorded for replayed iterations.                          */
   int precond_reuse;    /* CG with precond_rank > 0: the pivoted-Cholesky factor L built by
                            one solve may serve up to this many later solves on the same X
-                           (pointer, n, d) and rank before it is rebuilt; 0 = rebuild in
-                           every solve.  A reused L still defines an exact SPD
+                           (same pointer, same contents by a fingerprint taken at each
+                           solve, same n and d) and rank before it is rebuilt; 0 = rebuild
+                           in every solve.  A reused L still defines an exact SPD
                            P = L L^T + sigma^2 I with the current sigma (only the k x k
                            Woodbury factor is recomputed), so the accepted solutions meet
                            the same residual test; only the iteration count can differ. */
