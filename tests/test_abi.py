@@ -89,3 +89,23 @@ def test_no_gpu_means_an_error_not_a_fallback():
     from paper_2405_18457_amd import api
     with pytest.raises(Exception):
         api.Context(0)
+
+
+def test_every_context_call_rejects_a_null_context():
+    # Checked before any HIP call, so it runs without a GPU: every entry point
+    # that takes a context returns GP_ERR_INVALID_ARG for NULL instead of
+    # dereferencing it.
+    import ctypes as C
+    L = N.lib()
+    checked = []
+    for name in N.EXPORTS:
+        f = getattr(L, name)
+        if f.restype is not C.c_int or not f.argtypes or f.argtypes[0] is not C.c_void_p:
+            continue
+        args = [0 if t in (C.c_int, C.c_int64, C.c_double, C.c_uint64) else None
+                for t in f.argtypes]
+        assert f(*args) == N.GP_ERR_INVALID_ARG, name
+        checked.append(name)
+    assert len(checked) == 12, checked
+    assert L.gp_last_error(None) == b"null context"
+    L.gp_ctx_destroy(None)
