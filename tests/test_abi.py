@@ -109,3 +109,12 @@ def test_every_context_call_rejects_a_null_context():
     assert len(checked) == 12, checked
     assert L.gp_last_error(None) == b"null context"
     L.gp_ctx_destroy(None)
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    # no CPU or Python fallback: without the built library every call path
+    # stops at the loader with an ImportError that names the build step
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "libgpmi.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        N.lib()
