@@ -43,3 +43,15 @@ def test_four_pcg_steps_amplify_kernel_entry_errors():
     large = _moved(4000, 1000, 57, eps)
     assert small < 2e-4, small
     assert 2e-4 < large < 5e-3, large
+
+
+def test_budgeted_cg_steps_are_insensitive_to_kernel_entry_errors():
+    # the inputs of test_cg_budget_warm_start_and_scaling: three unpreconditioned
+    # CG steps move by about 0.41 eps of max|U|, so the 2e-4 bound of that test
+    # holds with a wide margin even at a 2^-16 error per kernel entry
+    X, B, theta = problem(900, 3, 9, seed=3, dist="uniform", sigma=0.05, ell_scale=(0.2, 0.5))
+    op = solvers.DenseOperator(X, theta)
+    U0, _ = solvers.cg(op, B, tol=1e-6, max_epochs=3)
+    U1, _ = solvers.cg(_Dense(_perturbed(op.H, 2.0 ** -16, 1)), B, tol=1e-6, max_epochs=3)
+    moved = float(np.abs(U1 - U0).max() / np.abs(U0).max())
+    assert moved < 2e-4 / 10, moved
