@@ -18,7 +18,8 @@ Forms:
   bf16x3+adjoint  products on bf16 MFMA with hi/lo splitting, FP32 true-residual
                   acceptance, one fused adjoint pass for the gradient (the value).
   fp32-plain      FP32 products, d+1 separate derivative-kernel passes for the
-                  gradient (reported alongside with --compare).
+                  gradient; by default one step of each form is timed after
+                  the timed region, from the same state, for the ratio.
 
 Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
 """
@@ -46,6 +47,13 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # an FP32 FMA is one slot (2 flops); v_sqrt_f32 / v_exp_f32 are half rate on gfx950
 # (measured: 8.5 vs 4.6 SIMD cycles per wave64 instruction), i.e. 2 slots each.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Vector-ALU instructions the dominant kernel issues per kernel entry, from its
+# counters (SQ_INSTS_VALU - SQ_INSTS_MFMA, SQ_INSTS_VALU_TRANS_F32, per wave-step
+# of 64 rows x 32 columns): simple ops, and transcendentals (sqrt, exp2).
+VALU_SIMPLE_PER_ENTRY = 5.5
+VALU_TRANS_PER_ENTRY = 2.0
+# contraction length of the squared-distance MFMA at d <= 3 ([-2x, |x|^2] . [x, 1])
+XT_KDIM = 4
 # HBM bytes per launch of the dominant kernel from two counter passes (FETCH_SIZE,
 # then WRITE_SIZE) over `bench.py --kernel-only 2`, each scaled by the same
 # counter's reading for the plain 1 GiB device copy of `bench.py --copy-probe 1024`
@@ -63,10 +71,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["bf16x3+adjoint", "fp32-plain"], default="bf16x3+adjoint")
-    ap.add_argument("--compare", action="store_true", help="also time the fp32-plain form")
+    ap.add_argument("--compare-steps", type=int, default=1,
+                    help="after the timed region, time this many steps of both forms from the "
+                         "same state (warm start, Adam moments, cached factor) for the metric's "
+                         "bf16x3+adjoint / fp32-plain ratio (0 = skip)")
     ap.add_argument("--n", type=int, default=None, help="override n (smaller runs; not the metric)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--cpu-rows-1core", type=int, default=128)
     ap.add_argument("--kernel-only", type=int, default=0, metavar="K",
                     help="only time K launches of the forward product on the bench inputs "
                          "(65 columns, same launch configuration); for profilers")
@@ -143,7 +155,7 @@ def probe_scaling(args):
     n = inp["n"]
     prec = {"bf16x3": api.GP_BF16X3, "fp32": api.GP_FP32, "bf16": api.GP_BF16}[args.precision]
     base = None
-    for c in (1, 9, 17, 33, 65, 129, 256):
+    for c in (1, 9, 17, 33, 65, 129, 257):
         V = dev(np.random.default_rng(c).standard_normal((n, c)).astype(np.float32))
         out = torch.empty_like(V)
         api.gp_kmatvec(ctx, inp["X"], inp["X"], inp["theta_true"], V, prec, True, out)
@@ -278,27 +290,24 @@ def build_targets(ctx, inp, tr, dev):
 def run_form(ctx, inp, y, form, steps, warmup, precond_rank, precond_reuse=0):
     import torch
     from paper_2405_18457_amd import api
-    prec = api.GP_BF16X3 if form == "bf16x3+adjoint" else api.GP_FP32
-    mode = api.GP_ADJ_FUSED if form == "bf16x3+adjoint" else api.GP_ADJ_PER_PARAM
-    cfg = api.solver_cfg(solver=api.GP_CG, tol=1e-2, precision=prec, precond_rank=precond_rank,
-                         precond_reuse=precond_reuse)
+    cfg, mode = _form_cfg(form, precond_rank, precond_reuse)
     tr = api.Trainer(ctx, inp["X"], y, inp["theta_true"], api.GP_PATHWISE, cfg, lr=0.03,
                      s=inp["w"].s, transform=api.GP_SOFTPLUS, warm=True, rff_t=inp["t"],
                      rff_W=inp["W"], w_eps=inp["w_eps"], adjoint_mode=mode)
     log = []
     for k in range(warmup):
         t0 = time.perf_counter()
-        _, _, st = tr.step()
+        th, _, st = tr.step()
         torch.cuda.synchronize()
-        log.append({"phase": "warmup", "s": time.perf_counter() - t0, **_brief(st)})
+        log.append({"phase": "warmup", "s": time.perf_counter() - t0, **_brief(st, th)})
         print(f"[bench] {form} warmup {k}: {log[-1]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
     for k in range(steps):
         ts = time.perf_counter()
-        _, _, st = tr.step()
-        log.append({"phase": "timed", "s": time.perf_counter() - ts, **_brief(st)})
+        th, _, st = tr.step()
+        log.append({"phase": "timed", "s": time.perf_counter() - ts, **_brief(st, th)})
         print(f"[bench] {form} step {k}: {log[-1]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -307,8 +316,57 @@ def run_form(ctx, inp, y, form, steps, warmup, precond_rank, precond_reuse=0):
     return elapsed, log, prof, tr
 
 
-def _brief(st):
-    return {"iters": st["iterations"], "matvecs": st["matvecs"], "refine": st["refinements"],
+def _form_cfg(form, precond_rank, precond_reuse):
+    from paper_2405_18457_amd import api
+    prec = api.GP_BF16X3 if form == "bf16x3+adjoint" else api.GP_FP32
+    mode = api.GP_ADJ_FUSED if form == "bf16x3+adjoint" else api.GP_ADJ_PER_PARAM
+    return api.solver_cfg(solver=api.GP_CG, tol=1e-2, precision=prec, precond_rank=precond_rank,
+                          precond_reuse=precond_reuse), mode
+
+
+def compare_forms(ctx, inp, y, trainer, steps, precond_rank):
+    """The metric's comparison on identical marginal-likelihood steps: from the state
+    the timed region ended in (warm-start solution, Adam moments and the cached
+    pivoted-Cholesky factor, which both forms reuse without rebuilding), `steps`
+    steps of the bf16x3+adjoint form and then the same steps of the fp32-plain form
+    (FP32 products, d+1 separate derivative passes for the gradient)."""
+    import copy
+
+    import torch
+    from paper_2405_18457_amd import api
+    U0 = trainer.U.clone()
+    state0 = copy.deepcopy(trainer.state)
+    res = {}
+    for form in ("bf16x3+adjoint", "fp32-plain"):
+        cfg, mode = _form_cfg(form, precond_rank, 1 << 30)
+        tr = api.Trainer(ctx, inp["X"], y, trainer.theta, api.GP_PATHWISE, cfg, lr=0.03,
+                         s=inp["w"].s, transform=api.GP_SOFTPLUS, warm=True, rff_t=inp["t"],
+                         rff_W=inp["W"], w_eps=inp["w_eps"], adjoint_mode=mode)
+        tr.U.copy_(U0)
+        tr.state = copy.deepcopy(state0)
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        log = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            th, _, st = tr.step()
+            log.append({"phase": "compare", "s": time.perf_counter() - ts, **_brief(st, th)})
+            print(f"[bench] compare {form} step {k}: {log[-1]}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        prof = {k: ctx.profile_read(k) for k in range(6)}
+        ctx.profile_enable(False)
+        res[form] = {"value": round(steps / elapsed, 6), "unit": "steps/s",
+                     "ms_per_step": round(1e3 * elapsed / steps, 1), "per_step": log,
+                     "kernel_ms": {"fwd_bf16": prof[0], "adjoint": prof[1], "fwd_fp32": prof[4],
+                                   "precond": prof[5]}}
+    return res
+
+
+def _brief(st, theta=None):
+    extra = {} if theta is None else {"theta": [round(float(v), 5) for v in theta]}
+    return {**extra, "iters": st["iterations"], "matvecs": st["matvecs"], "refine": st["refinements"],
             "precond_rank": st["precond_rank"],
             "relres_y": round(st["true_relres_y"], 5) if st["true_relres_y"] == st["true_relres_y"]
             else round(st["relres_y"], 5),
@@ -329,60 +387,81 @@ def traffic_per_launch():
 
 
 def roofline(n, d, c, prof):
-    """Dominant kernel: the bf16x3 forward product (class 0)."""
+    """Dominant kernel: the bf16x3 forward product (profile class 0).
+
+    `achieved` is the algorithmic K*V work of one product, 2 c n^2 flops with
+    c = s + 1 columns (every kernel entry multiplies every column once), over the
+    average launch time, against the bf16 matrix-core peak.  The kernel issues
+    three bf16 passes per tile (hi*hi + hi*lo + lo*hi) over 80 padded columns and
+    the squared distances on the FP32 matrix cores; `mfma_issued` reports that
+    busy time, and `valu` the vector-ALU work the kernel issues per entry."""
     ms, cnt = prof[0]
     if cnt == 0:
         return None
     avg_s = ms / cnt / 1e3
     entries = float(n) * n
-    # Algorithmic VALU work per kernel entry, counted for the plain definition
-    # (direct differences; the kernel moves the squared distance onto the matrix
-    # cores for d <= 3, which this count does not credit): d subtractions + d
-    # FMAs for r^2, fma + mul for (1 + ln2 rho) 2^-rho, and one sqrt + one exp2
-    # at 2 slots each.
-    slots_per_entry = 2 * d + 2 + 2 * 2
-    achieved = entries * slots_per_entry / avg_s          # VALU lane-slots per second
-    mfma_tflops = 2.0 * c * entries / avg_s / 1e12        # algorithmic K*V flops (c = s + 1)
+    kv_flops = 2.0 * c * entries
+    achieved = kv_flops / avg_s / 1e12
+    c_pad = 16 * ((c + 15) // 16)
+    t_bf16 = 3 * 2.0 * c_pad * entries / (BF16_PEAK_TFLOPS * 1e12)
+    t_xt = 2.0 * XT_KDIM * entries / (FP32_MFMA_PEAK_TFLOPS * 1e12)
+    slots = entries * (VALU_SIMPLE_PER_ENTRY + 2.0 * VALU_TRANS_PER_ENTRY)
     return {
-        "bound": "alu",
-        "achieved": round(achieved * 2 / 1e12, 3),        # reported as FP32 TFLOP/s (1 slot = 2 flops)
-        "peak": round(VALU_SLOTS_PER_S * 2 / 1e12, 3),
+        "bound": "mfma",
+        "achieved": round(achieved, 2),
+        "peak": BF16_PEAK_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": round(achieved / VALU_SLOTS_PER_S, 4),
+        "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
         "traffic": traffic_per_launch(),
         "kernel": "kfwd_bf16_xt<BF16X3, CT=5, RS=4>",
+        "flops_per_launch": kv_flops,
         "avg_launch_ms": round(avg_s * 1e3, 3),
         "launches": cnt,
         "kernel_entries_per_s": round(entries / avg_s, 1),
-        "mfma_kv_tflops": round(mfma_tflops, 2),
-        "mfma_kv_frac_of_bf16_peak": round(mfma_tflops / BF16_PEAK_TFLOPS, 4),
+        "mfma_issued": {"bf16_passes": 3, "columns_padded": c_pad,
+                        "busy_ms_at_peak": round(1e3 * (t_bf16 + t_xt), 2),
+                        "busy_frac": round((t_bf16 + t_xt) / avg_s, 4)},
+        "valu": {"slots_per_entry": VALU_SIMPLE_PER_ENTRY + 2.0 * VALU_TRANS_PER_ENTRY,
+                 "achieved_slots_per_s": round(slots / avg_s, 1),
+                 "peak_slots_per_s": VALU_SLOTS_PER_S,
+                 "frac": round(slots / avg_s / VALU_SLOTS_PER_S, 4)},
     }
 
 
-def cpu_baseline(inp, iters_per_step, rows, y_host=None):
-    """The oracle's matrix-free FP64 product on a bounded row sample, scaled to a step."""
+def cpu_baseline(inp, iters_per_step, rows, rows_1core):
+    """The oracle's matrix-free FP64 product on a bounded row sample, scaled to a step:
+    once with every BLAS thread the host gives it, once on one core."""
     import oracle.kernel as ok
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     X = inp["Xh"]
     n = X.shape[0]
     theta = inp["theta_true"]
     V = np.random.default_rng(0).standard_normal((n, inp["w"].s + 1))
-    idx = np.arange(rows)
-    t0 = time.perf_counter()
-    ok.k_matvec(X[idx], X, theta, V)
-    dt = time.perf_counter() - t0
-    t_matvec = dt * n / rows
-    # per step: iterations + initial/true-residual products + one adjoint (~ one product)
-    t_step = (iters_per_step + 3) * t_matvec
+
+    def timed(r):
+        t0 = time.perf_counter()
+        ok.k_matvec(X[:r], X, theta, V)
+        return time.perf_counter() - t0
+
+    def per_step(dt, r):
+        t_matvec = dt * n / r
+        # per step: iterations + initial/true-residual products + one adjoint (~ one product)
+        return t_matvec, (iters_per_step + 3) * t_matvec
+
+    dt = timed(rows)
+    t_mv, t_step = per_step(dt, rows)
+    with threadpool_limits(limits=1):
+        dt1 = timed(rows_1core)
+    t_mv1, t_step1 = per_step(dt1, rows_1core)
     return {"value": float(f"{1.0 / t_step:.4g}"), "unit": "steps/s", "cores": int(blas_threads),
             "kind": "oracle",
             "sample": f"FP64 matrix-free H*V on {rows} of {n} rows x 65 columns took {dt:.2f} s; "
-                      f"full product extrapolated to {t_matvec:.1f} s; step = (CG iterations "
-                      f"{iters_per_step:.1f} + 3) products"}
+                      f"full product extrapolated to {t_mv:.1f} s; step = (CG iterations "
+                      f"{iters_per_step:.1f} + 3) products",
+            "one_core": {"value": float(f"{1.0 / t_step1:.4g}"), "unit": "steps/s", "cores": 1,
+                         "sample": f"{rows_1core} rows on one BLAS thread took {dt1:.2f} s; "
+                                   f"full product extrapolated to {t_mv1:.1f} s"}}
 
 
 def main():
@@ -421,7 +500,7 @@ def main():
         "metric": METRIC, "value": round(value, 6), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if args.form == "bf16x3+adjoint" else "fp32",
+        "dtype": "bf16x3" if args.form == "bf16x3+adjoint" else "fp32",
         "data": "synthetic",
         "config": {"workload": f"precision workload: n={n}, d={d}, x~U[-1,1]^3, ell~U[0.05,0.2], "
                                f"sigma=0.05, s={s}, pathwise + warm start, CG to rel-res 1e-2, "
@@ -446,15 +525,16 @@ def main():
                                     "unit": "TFLOP/s", "frac": round(tf / FP32_MFMA_PEAK_TFLOPS, 4)}
     rec["kernel_ms"] = {"fwd_bf16": prof[0], "adjoint": prof[1], "rff": prof[2], "cg_vec": prof[3],
                         "fwd_fp32": prof[4], "precond": prof[5]}
-    if args.compare:
-        e2, log2, prof2, _ = run_form(ctx, inp, y, "fp32-plain", args.steps, args.warmup,
-                                      args.precond_rank, args.precond_reuse)
-        rec["fp32_plain"] = {"value": round(args.steps / e2, 6), "unit": "steps/s",
-                             "per_step": [r for r in log2 if r["phase"] == "timed"],
-                             "kernel_ms": {"fwd_fp32": prof2[4]}}
-        rec["bf16x3_over_fp32_plain"] = round(value / (args.steps / e2), 3)
+    if args.compare_steps > 0:
+        cmp = compare_forms(ctx, inp, y, trainer, args.compare_steps, args.precond_rank)
+        rec["compare"] = {
+            "note": "the same marginal-likelihood step(s) in both forms, from the state the "
+                    "timed region ended in, both reusing its cached preconditioner factor",
+            **cmp,
+            "bf16x3_adjoint_over_fp32_plain": round(cmp["bf16x3+adjoint"]["value"]
+                                                    / cmp["fp32-plain"]["value"], 3)}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(inp, iters, args.cpu_rows)
+        rec["cpu_baseline"] = cpu_baseline(inp, iters, args.cpu_rows, args.cpu_rows_1core)
     print(json.dumps(rec), flush=True)
 
 

@@ -26,7 +26,9 @@
  *  - Return value: GP_OK or an error code; gp_last_error() gives the text.
  *    On error, device outputs are unspecified and no state is leaked.
  *  - The library allocates its workspace with hipMalloc on first use and
- *    grows it when a larger problem arrives (never inside a solver loop).
+ *    grows it when a larger problem arrives (never inside a solver loop);
+ *    gp_workspace_size tells its size and gp_workspace_reserve allocates it
+ *    up front.
  */
 #ifndef GP_H
 #define GP_H
@@ -113,7 +115,9 @@ int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches)
  *   add_noise requires n1 == n2 and X1 describing the same points as X2.
  * n1 = 0 or n2 = 0 or c = 0 is a no-op (out untouched; with n2 = 0 and
  * n1 > 0 the first c columns of out are set to zero).
- * Errors: GP_ERR_INVALID_ARG for d < 1, d > 64, c > 256, ld < c, theta <= 0,
+ * Columns go through the kernel in passes of at most 80; every pass evaluates
+ * the kernel entries again, so c is limited only by the workspace.
+ * Errors: GP_ERR_INVALID_ARG for d < 1, d > 64, c > 1024, ld < c, theta <= 0,
  * a NULL pointer with a non-empty size.                                     */
 int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_t n2, int d,
                const double* theta, const float* V, int64_t ldv, int c, float* out, int64_t ldo,
@@ -126,6 +130,8 @@ int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_
  *   U [n, ldu], W [n, ldw]: first c columns used.  col_weights: HOST [c].
  *   precision: GP_FP32 or GP_BF16X3 for the U diag(w) W^T tile products.
  *   mode: gp_adjoint_mode.  grad_out: HOST [d+2] doubles.
+ * The fused pass takes up to 256 columns; more columns (up to 1024) run as
+ * several passes whose sums are added.
  * Errors as gp_kmatvec.                                                     */
 int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
                        const float* U, int64_t ldu, const float* W, int64_t ldw, int c,
@@ -197,6 +203,9 @@ void gp_solver_cfg_default(gp_solver_cfg* cfg);
  *   cold start, the previous solution for a warm start), OUT: solution.
  *   cfg, stats: HOST structs (stats may be NULL).
  * Not reaching tol within the budget is not an error (stats->converged = 0).
+ * At most 256 columns (the per-column scalar reductions of one iteration run
+ * one thread per column in one 256-thread block); gp_mll_grad likewise takes
+ * s <= 255 probes.
  * Errors: GP_ERR_INVALID_ARG, GP_ERR_NONFINITE, GP_ERR_BREAKDOWN, GP_ERR_HIP. */
 int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
              const float* B, int64_t ldb, float* U, int64_t ldu, int c,
@@ -215,6 +224,40 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
  * Errors: GP_ERR_INVALID_ARG (k > 8192, ldl < n, NULL pointers), GP_ERR_HIP. */
 int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
                         int k, double* L, int64_t ldl, int32_t* piv, int* rank);
+
+/* ---------------------------------------------------------------- workspace */
+
+/* Operations whose device workspace can be planned (the buffers the library
+ * keeps between calls: packed inputs, bf16 operand tiles, column-split partial
+ * sums, solver vectors and scalars, the preconditioner factor).             */
+enum gp_ws_op {
+  GP_WS_KMATVEC = 0,  /* gp_kmatvec H V with X1 == X2 (cfg->precision; cfg may be NULL
+                         for GP_FP32)                                             */
+  GP_WS_SOLVE = 1,    /* gp_solve with *cfg                                      */
+  GP_WS_MLL_GRAD = 2  /* gp_mll_grad with *cfg, s = c - 1 probes and M random-feature
+                         pairs (M = 0 for the standard estimator), either adjoint mode */
+};
+
+/* Bytes of device memory a context holds after one call of `op` on n points in
+ * d dimensions with c columns: the operator, its solver iterations and right-hand
+ * sides are the Require lines of App. B, Algorithms 1-3 (H, b and the solver's
+ * vectors).  Where a size depends on the data (the squared-distance form, the
+ * preconditioner rank reached) the larger case is counted, so the figure is an
+ * upper bound for that call.  Host-only: no context or device needed.
+ * Errors: GP_ERR_INVALID_ARG for an unknown op, a NULL bytes or cfg (where
+ * needed), or sizes the operation itself rejects.                            */
+int gp_workspace_size(int op, int64_t n, int d, int c, const gp_solver_cfg* cfg, int M,
+                      size_t* bytes);
+
+/* Allocate, now, the workspace gp_workspace_size counts, on ctx's device: later
+ * calls of `op` of at most this size allocate nothing (buffers only grow).
+ * Errors: as gp_workspace_size; GP_ERR_NO_WORKSPACE, GP_ERR_HIP.             */
+int gp_workspace_reserve(gp_ctx* ctx, int op, int64_t n, int d, int c,
+                         const gp_solver_cfg* cfg, int M);
+
+/* Bytes of device workspace ctx holds now (*bytes; host).  Errors:
+ * GP_ERR_INVALID_ARG for NULL arguments.                                    */
+int gp_workspace_held(const gp_ctx* ctx, size_t* bytes);
 
 /* --------------------------------------------------------- random features */
 
@@ -279,6 +322,13 @@ int gp_adam_ascent(int p, double* nu, double* m, double* v, int64_t* step,
 
 /* theta[k] = softplus(nu[k]) or exp(nu[k]) (HOST arrays [p]). */
 int gp_nu_to_theta(int p, const double* nu, int transform, double* theta);
+
+/* The inverse: nu[k] = softplus^-1(theta[k]) = theta[k] + log(1 - exp(-theta[k]))
+ * or log(theta[k]) (HOST arrays [p]), the unconstrained starting point of the
+ * optimiser for hyperparameters theta > 0 (App. B, "Iterative Optimiser").
+ * Errors: GP_ERR_INVALID_ARG for p < 0, NULL arrays, an unknown transform or
+ * a theta[k] that is not finite and positive.                              */
+int gp_theta_to_nu(int p, const double* theta, int transform, double* nu);
 
 /* ------------------------------------ initial hyperparameters (large data) */
 

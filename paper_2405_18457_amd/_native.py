@@ -16,6 +16,7 @@ GP_CG, GP_AP, GP_SGD = 0, 1, 2
 GP_STANDARD, GP_PATHWISE = 0, 1
 GP_ADJ_FUSED, GP_ADJ_PER_PARAM = 0, 1
 GP_SOFTPLUS, GP_LOG = 0, 1
+GP_WS_KMATVEC, GP_WS_SOLVE, GP_WS_MLL_GRAD = 0, 1, 2
 
 STATUS_NAMES = {
     GP_OK: "ok", GP_ERR_INVALID_ARG: "invalid_arg", GP_ERR_HIP: "hip",
@@ -27,8 +28,9 @@ STATUS_NAMES = {
 EXPORTS = (
     "gp_ctx_create", "gp_ctx_destroy", "gp_last_error", "gp_version", "gp_profile_enable",
     "gp_profile_read", "gp_kmatvec", "gp_kmatvec_adjoint", "gp_solver_cfg_default", "gp_solve",
-    "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_pivoted_cholesky",
+    "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_theta_to_nu", "gp_pivoted_cholesky",
     "gp_posterior_sample", "gp_nearest", "gp_exact_mll", "gp_init_cfg_default", "gp_init_heuristic",
+    "gp_workspace_size", "gp_workspace_reserve", "gp_workspace_held",
 )
 
 
@@ -95,6 +97,7 @@ def lib():
                                   C.POINTER(SolveStats)]),
             "gp_adam_ascent": (i32, [i32, pd, pd, pd, pi64, pd, dbl, i32]),
             "gp_nu_to_theta": (i32, [i32, pd, i32, pd]),
+            "gp_theta_to_nu": (i32, [i32, pd, i32, pd]),
             "gp_pivoted_cholesky": (i32, [vp, vp, i64, i32, pd, i32, vp, i64, vp,
                                           C.POINTER(C.c_int)]),
             "gp_posterior_sample": (i32, [vp, vp, i64, vp, i64, i32, pd, vp, i32, vp, i64, vp,
@@ -104,6 +107,10 @@ def lib():
             "gp_init_cfg_default": (None, [C.POINTER(InitCfg)]),
             "gp_init_heuristic": (i32, [vp, vp, i64, i32, vp, pi64, i32, i64, C.POINTER(InitCfg),
                                         pd, pd]),
+            "gp_workspace_size": (i32, [i32, i64, i32, i32, C.POINTER(SolverCfg), i32,
+                                        C.POINTER(C.c_size_t)]),
+            "gp_workspace_reserve": (i32, [vp, i32, i64, i32, i32, C.POINTER(SolverCfg), i32]),
+            "gp_workspace_held": (i32, [vp, C.POINTER(C.c_size_t)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

@@ -14,8 +14,8 @@ import torch
 
 from . import _native as N
 from ._native import (GP_ADJ_FUSED, GP_ADJ_PER_PARAM, GP_AP, GP_BF16, GP_BF16X3, GP_CG,  # noqa: F401
-                      GP_FP32, GP_LOG, GP_PATHWISE, GP_SGD, GP_SOFTPLUS, GP_STANDARD, InitCfg,
-                      SolveStats, SolverCfg)
+                      GP_FP32, GP_LOG, GP_PATHWISE, GP_SGD, GP_SOFTPLUS, GP_STANDARD,
+                      GP_WS_KMATVEC, GP_WS_MLL_GRAD, GP_WS_SOLVE, InitCfg, SolveStats, SolverCfg)
 
 
 class GPError(RuntimeError):
@@ -310,6 +310,37 @@ def gp_nu_to_theta(nu, transform=GP_SOFTPLUS):
     return th
 
 
+def gp_workspace_size(op, n, d, c, cfg: SolverCfg | None = None, M=0):
+    """Device bytes a context holds after one call of op (N.GP_WS_*) of this size."""
+    out = C.c_size_t()
+    rc = N.lib().gp_workspace_size(op, n, d, c, C.byref(cfg) if cfg is not None else None, M,
+                                   C.byref(out))
+    if rc != N.GP_OK:
+        raise GPError(rc, "gp_workspace_size")
+    return out.value
+
+
+def gp_workspace_reserve(ctx: Context, op, n, d, c, cfg: SolverCfg | None = None, M=0):
+    ctx.check(N.lib().gp_workspace_reserve(ctx.handle, op, n, d, c,
+                                           C.byref(cfg) if cfg is not None else None, M))
+
+
+def gp_workspace_held(ctx: Context):
+    out = C.c_size_t()
+    ctx.check(N.lib().gp_workspace_held(ctx.handle, C.byref(out)))
+    return out.value
+
+
+def gp_theta_to_nu(theta, transform=GP_SOFTPLUS):
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    nu = np.zeros_like(th)
+    pd = C.POINTER(C.c_double)
+    rc = N.lib().gp_theta_to_nu(th.size, th.ctypes.data_as(pd), transform, nu.ctypes.data_as(pd))
+    if rc != N.GP_OK:
+        raise GPError(rc, "gp_theta_to_nu")
+    return nu
+
+
 def gp_adam_ascent(state: dict, grad_theta, lr, transform=GP_SOFTPLUS):
     """In-place Adam ascent on state['nu'] (state holds nu, m, v float64 arrays and 'step')."""
     pd = C.POINTER(C.c_double)
@@ -361,8 +392,7 @@ class Trainer:
         self.estimator, self.cfg, self.lr, self.transform = estimator, cfg, lr, transform
         self.warm, self.adjoint_mode = warm, adjoint_mode
         self.Z, self.rff_t, self.rff_W, self.w_eps = Z, rff_t, rff_W, w_eps
-        th0 = np.asarray(theta0, dtype=np.float64)
-        nu0 = np.log(th0) if transform == GP_LOG else th0 + np.log(-np.expm1(-th0))
+        nu0 = gp_theta_to_nu(theta0, transform)
         self.state = {"nu": nu0.copy(), "m": np.zeros_like(nu0), "v": np.zeros_like(nu0), "step": 0}
         self.U = torch.zeros((X.shape[0], s + 1), device=X.device, dtype=torch.float32)
         self.history = []

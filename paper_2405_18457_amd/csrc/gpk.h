@@ -24,6 +24,7 @@ constexpr float kLn2 = 0.693147180559945309f;
 constexpr int kRowAlign = 256;
 constexpr int kJStep = 32;          // forward kernel: kernel columns per MFMA K-chunk
 constexpr int kAdjRowsPerWG = 128;
+constexpr int kAdjMaxCols = 256;  // columns of one fused-adjoint pass (8 K-tiles of 32)
 // Row sub-tiles of 16 rows per wave in the forward kernel (4 waves per
 // workgroup): 4 for up to 5 column tiles (80 columns), 2 for wider products.
 constexpr int fwd_row_subtiles(int CT) { return CT <= 5 ? 4 : 2; }
@@ -33,7 +34,9 @@ constexpr int xt_chunks(int d) { return (d + 1 + 3) / 4; }
 constexpr int fwd_xt_row_subtiles(int CT, int NK) { return (CT <= 5 && NK <= 3) ? 4 : 2; }
 inline int fwd_rows_per_wg(int CT) { return 64 * fwd_row_subtiles(CT); }
 constexpr int kMaxD = 64;
-constexpr int kMaxC = 256;
+constexpr int kMaxC = 1024;      // columns of a product, adjoint or random-feature sample
+constexpr int kMaxSolveC = 256;  // columns of a solve: the column reductions run one
+                                 // thread per column in a 256-thread block
 
 enum Prec { P_FP32 = 0, P_BF16X3 = 1, P_BF16 = 2 };
 enum Fn { FN_MATERN = 0, FN_DLEN = 1 };

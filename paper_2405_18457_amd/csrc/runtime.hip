@@ -188,9 +188,9 @@ int check_theta(gp_ctx* ctx, const double* theta, int d) {
   return GP_OK;
 }
 
-int check_dims(gp_ctx* ctx, int d, int c) {
+int check_dims(gp_ctx* ctx, int d, int c, int cmax = kMaxC) {
   if (d < 1 || d > kMaxD) return fail(ctx, GP_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
-  if (c < 0 || c > kMaxC) return fail(ctx, GP_ERR_INVALID_ARG, "c = %d outside [0, %d]", c, kMaxC);
+  if (c < 0 || c > cmax) return fail(ctx, GP_ERR_INVALID_ARG, "c = %d outside [0, %d]", c, cmax);
   return GP_OK;
 }
 
@@ -342,10 +342,15 @@ int col_sums(gp_ctx* ctx, const float* A, const float* B, int64_t n, int64_t lda
   }
   const int nb = reduce_blocks(n);
   double *partial, *res;
-  CHK(ensure(ctx, B_PARTIAL, (size_t)nb * c, &partial));
+  CHK(ensure(ctx, B_PARTIAL, (size_t)nb * std::min(c, kMaxSolveC), &partial));
   CHK(ensure(ctx, B_SCALD, (size_t)6 * kMaxC, &res));
-  HIPCHK(col_dot_partial(A, B, n, lda, ldb, c, partial, nb, ctx->stream));
-  HIPCHK(col_reduce(partial, nb, c, res + 5 * kMaxC, ctx->stream));
+  // the column reductions take at most kMaxSolveC columns per launch
+  for (int c0 = 0; c0 < c; c0 += kMaxSolveC) {
+    const int cs = std::min(kMaxSolveC, c - c0);
+    HIPCHK(col_dot_partial(A + c0, B ? B + c0 : nullptr, n, lda, ldb, cs, partial, nb,
+                           ctx->stream));
+    HIPCHK(col_reduce(partial, nb, cs, res + 5 * kMaxC + c0, ctx->stream));
+  }
   CHK(ensure_pinned(ctx, kMaxC));
   HIPCHK(hipMemcpyAsync(ctx->hpin, res + 5 * kMaxC, c * sizeof(double), hipMemcpyDeviceToHost,
                         ctx->stream));
@@ -967,6 +972,189 @@ int solve_dispatch(gp_ctx* ctx, const Packed& px, const float* X, const double* 
                    const float* B, int64_t ldb, float* U, int64_t ldu, int c,
                    const gp_solver_cfg& cfg, gp_solve_stats& stats);
 
+// ------------------------------------------------------------ workspace plan
+// The largest request every workspace buffer receives during one call of an
+// operation, in bytes, computed with the same counts as the ensure() calls of
+// the code paths above (pack_points, kprod, solve_setup, the solvers, the
+// preconditioner, the right-hand sides and the adjoint).  Where a size depends
+// on the data (the cross-term distance form, the rank the factor reaches) the
+// larger case is planned.
+struct WsPlan {
+  size_t bytes[B_COUNT] = {};
+  size_t pinned = kMaxC + 2;  // doubles of pinned host staging (norm reads)
+  void need(BufId id, size_t b) { bytes[id] = std::max(bytes[id], b); }
+  void need_pinned(size_t doubles) { pinned = std::max(pinned, doubles); }
+  size_t held() const {
+    // ensure() allocates max(bytes, 256) plus one eighth
+    size_t t = 0;
+    for (size_t b : bytes)
+      if (b) {
+        const size_t v = std::max<size_t>(b, 256);
+        t += v + v / 8;
+      }
+    return t;
+  }
+};
+
+void plan_pack(WsPlan& p, BufId id, int64_t n, int d) {
+  const int64_t n_pad = round_up(std::max<int64_t>(n, 1), kRowAlign);
+  const int D = select_D(d);
+  p.need(id, (size_t)(n_pad * dp_of(D)) * sizeof(float));
+  if (D > 3)
+    p.need(id == B_XP1 ? B_XT1 : B_XT2, (size_t)(n_pad * 4 * xt_chunks(D)) * sizeof(float));
+  p.need(B_XTMAX, 3 * sizeof(unsigned));
+}
+
+void plan_kprod(WsPlan& p, int64_t n1, int64_t n2, int d, int cols, int prec) {
+  const int64_t n1_pad = round_up(std::max<int64_t>(n1, 1), kRowAlign);
+  const int64_t n2_pad = round_up(std::max<int64_t>(n2, 1), kRowAlign);
+  const int D = select_D(d);
+  const int npass = (cols + 79) / 80;
+  const int per = (cols + npass - 1) / npass;
+  for (int c0 = 0; c0 < cols; c0 += per) {
+    const int cs = std::min(per, cols - c0);
+    const int CT = select_CT(cs);
+    const size_t vcount = (size_t)(n2_pad * 16 * CT);
+    if (prec == GP_FP32) {
+      p.need(B_VHI, vcount * sizeof(float));
+    } else {
+      p.need(B_VHI, vcount * sizeof(uint16_t));
+      if (prec == GP_BF16X3) p.need(B_VLO, vcount * sizeof(uint16_t));
+    }
+    for (int xt = 0; xt < 2; ++xt) {
+      const int rs = xt ? fwd_xt_row_subtiles(CT, xt_chunks(D)) : fwd_row_subtiles(CT);
+      const int S = choose_splits(n1_pad / (64 * rs), n2_pad / kJStep);
+      if (S > 1) p.need(B_PART, (size_t)(S * n1_pad * 16 * CT) * sizeof(float));
+    }
+  }
+}
+
+void plan_col_sums(WsPlan& p, int64_t n, int c) {
+  p.need(B_PARTIAL, (size_t)reduce_blocks(n) * std::min(c, kMaxSolveC) * sizeof(double));
+  p.need(B_SCALD, (size_t)6 * kMaxC * sizeof(double));
+}
+
+void plan_solve(WsPlan& p, int64_t n, int d, int c, const gp_solver_cfg& cfg) {
+  plan_pack(p, B_XP1, n, d);
+  const size_t vec = (size_t)std::max<int64_t>(n, 1) * c * sizeof(float);
+  for (BufId id : {B_BT, B_UT, B_R, B_DV, B_HD}) p.need(id, vec);
+  p.need(B_SCALD, (size_t)6 * kMaxC * sizeof(double));
+  p.need(B_SCALF, (size_t)kMaxC * sizeof(float));
+  p.need(B_STATUS, 16 * sizeof(int));
+  p.need(B_PARTIAL, (size_t)reduce_blocks(n) * c * sizeof(double));
+  plan_kprod(p, n, n, d, c, GP_FP32);  // true residuals
+  plan_kprod(p, n, n, d, c, cfg.precision);
+  if (cfg.solver == GP_CG) {
+    const int k = (int)std::min<int64_t>(cfg.precond_rank, n);
+    if (k > 0) {
+      const int64_t ldl = round_up(n, 64);
+      const int kp = (int)round_up(k, 32);
+      p.need(B_Z, vec);
+      p.need(B_PCSUM, sizeof(unsigned long long));
+      p.need(B_PCL32, (size_t)k * ldl * sizeof(float));
+      p.need(B_PCPIV, (size_t)k * sizeof(int32_t));
+      p.need(B_PCDIAG, (size_t)n * sizeof(double));
+      p.need(B_PCLP, (size_t)k * sizeof(double));
+      p.need(B_PCPV, (size_t)pc_parts(n) * sizeof(double));
+      p.need(B_PCPI, (size_t)pc_parts(n) * sizeof(int64_t));
+      p.need(B_PCST, sizeof(PcState));
+      p.need(B_PCELL, (size_t)d * sizeof(double));
+      p.need(B_PCG, (size_t)k * k * sizeof(double));
+      p.need(B_PCA, (size_t)kp * kp * sizeof(double));
+      p.need(B_PCM, (size_t)kp * kp * sizeof(double));
+      p.need(B_PCW, (size_t)kp * kp * sizeof(double));
+      p.need(B_PCSTAT, sizeof(int));
+      const int64_t parts = std::max({pc_gram_parts(n, k), pc_inverse_parts(kp),
+                                      pc_apply_parts(n, k, c)});
+      p.need(B_PCPART, (size_t)parts * sizeof(double));
+      p.need(B_PCT, (size_t)k * c * sizeof(double));
+      p.need(B_PCS, (size_t)k * c * sizeof(double));
+    }
+  } else if (cfg.solver == GP_AP) {
+    const int b = (int)std::max<int64_t>(1, std::min<int64_t>(cfg.ap_block, n));
+    const int P = (int)round_up(b, 32);
+    const int nblk = (int)((n + b - 1) / b);
+    p.need(B_APF, (size_t)nblk * P * P * sizeof(double));
+    p.need(B_G, (size_t)P * c * sizeof(float));
+    p.need(B_AUX, vec);
+    p.need(B_ADJP, (size_t)nblk * sizeof(double));
+    p.need_pinned((size_t)kMaxC + 2 + nblk);
+    plan_pack(p, B_XP2, b, d);  // the selected block's points
+    plan_kprod(p, n, b, d, c, cfg.precision);
+  } else {
+    const int b = (int)std::max<int64_t>(1, std::min<int64_t>(cfg.sgd_batch, n));
+    p.need(B_MOM, vec);
+    p.need(B_G, (size_t)round_up(b, kRowAlign) * c * sizeof(float));
+    p.need(B_IDX, (size_t)b * 2 * sizeof(int32_t));
+    p.need(B_AUX, vec);
+    p.need_pinned((size_t)kMaxC + 2 + b);
+    plan_pack(p, B_XP2, b, d);
+    plan_kprod(p, b, n, d, c, cfg.precision);
+  }
+}
+
+void plan_adjoint(WsPlan& p, int64_t n, int d, int c, int precision) {
+  plan_pack(p, B_XP1, n, d);
+  plan_col_sums(p, n, c);
+  const int64_t n_pad = round_up(std::max<int64_t>(n, 1), kRowAlign);
+  const int D = select_D(d);
+  // per-parameter form
+  p.need(B_AUX, (size_t)n * c * sizeof(float));
+  plan_kprod(p, n, n, d, c, GP_FP32);
+  // fused form
+  p.need(B_SCALF, (size_t)kMaxC * sizeof(float));
+  for (int g0 = 0; g0 < c; g0 += kAdjMaxCols) {
+    const int CK = 32 * select_KT(std::min(kAdjMaxCols, c - g0));
+    const size_t pc = (size_t)(n_pad * CK);
+    if (precision == GP_BF16X3) {
+      for (BufId id : {B_UHI, B_ULO, B_WHI, B_WLO}) p.need(id, pc * sizeof(uint16_t));
+    } else {
+      p.need(B_UHI, pc * 2 * sizeof(uint16_t));
+      p.need(B_WHI, pc * 2 * sizeof(uint16_t));
+    }
+    const int64_t rowblocks = n_pad / kAdjRowsPerWG;
+    int S = 1;
+    while (rowblocks * S < 2048 && (n_pad / 16) / (2 * S) >= 32) S *= 2;
+    p.need(B_ADJP, (size_t)(rowblocks * S * (D + 1)) * sizeof(double));
+    p.need_pinned((size_t)(rowblocks * S * (D + 1)));
+  }
+}
+
+int ws_plan(int op, int64_t n, int d, int c, const gp_solver_cfg* cfg, int M, WsPlan& p,
+            gp_ctx* ctx) {
+  if (n < 0) return fail(ctx, GP_ERR_INVALID_ARG, "n < 0");
+  if (op == GP_WS_KMATVEC) {
+    CHK(check_dims(ctx, d, c));
+    const int prec = cfg ? cfg->precision : GP_FP32;
+    CHK(check_prec(ctx, prec));
+    if (n == 0 || c == 0) return GP_OK;
+    plan_pack(p, B_XP1, n, d);
+    plan_kprod(p, n, n, d, c, prec);
+    return GP_OK;
+  }
+  if (op != GP_WS_SOLVE && op != GP_WS_MLL_GRAD)
+    return fail(ctx, GP_ERR_INVALID_ARG, "unknown workspace operation %d", op);
+  if (!cfg) return fail(ctx, GP_ERR_INVALID_ARG, "cfg is NULL");
+  CHK(check_dims(ctx, d, c, kMaxSolveC));
+  CHK(check_prec(ctx, cfg->precision));
+  CHK(check_precond(ctx, *cfg));
+  if (cfg->solver != GP_CG && cfg->solver != GP_AP && cfg->solver != GP_SGD)
+    return fail(ctx, GP_ERR_INVALID_ARG, "solver %d not available", cfg->solver);
+  if (n == 0 || c == 0) return GP_OK;
+  plan_solve(p, n, d, c, *cfg);
+  if (op == GP_WS_MLL_GRAD) {
+    if (M < 0) return fail(ctx, GP_ERR_INVALID_ARG, "M = %d must be >= 0", M);
+    p.need(B_RHS, (size_t)n * c * sizeof(float));
+    p.need(B_WB, (size_t)n * c * sizeof(float));  // standard estimator
+    if (M > 0) {
+      p.need(B_OMEGA, (size_t)M * d * sizeof(double));
+      p.need(B_INVELL, (size_t)kMaxD * sizeof(double));
+    }
+    plan_adjoint(p, n, d, c, cfg->precision == GP_FP32 ? GP_FP32 : GP_BF16X3);
+  }
+  return GP_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1037,6 +1225,41 @@ int gp_profile_read(gp_ctx* ctx, int which, double* total_ms, int64_t* launches)
   CHK(harvest(ctx));
   if (total_ms) *total_ms = ctx->prof_ms[which];
   if (launches) *launches = ctx->prof_n[which];
+  return GP_OK;
+}
+
+int gp_workspace_size(int op, int64_t n, int d, int c, const gp_solver_cfg* cfg, int M,
+                      size_t* bytes) {
+  if (!bytes) return GP_ERR_INVALID_ARG;
+  WsPlan p;
+  const int r = ws_plan(op, n, d, c, cfg, M, p, nullptr);
+  if (r != GP_OK) return r;
+  *bytes = p.held();
+  return GP_OK;
+}
+
+int gp_workspace_reserve(gp_ctx* ctx, int op, int64_t n, int d, int c, const gp_solver_cfg* cfg,
+                         int M) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  WsPlan p;
+  CHK(ws_plan(op, n, d, c, cfg, M, p, ctx));
+  HIPCHK(hipSetDevice(ctx->device));
+  for (int id = 0; id < B_COUNT; ++id)
+    if (p.bytes[id]) {
+      unsigned char* ptr;
+      CHK(ensure(ctx, (BufId)id, p.bytes[id], &ptr));
+    }
+  // the pinned host staging of the solvers' norm reads and of the adjoint partials
+  CHK(ensure_pinned(ctx, p.pinned));
+  return GP_OK;
+}
+
+int gp_workspace_held(const gp_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return GP_ERR_INVALID_ARG;
+  size_t t = 0;
+  for (int id = 0; id < B_COUNT; ++id) t += ctx->cap[id];
+  *bytes = t;
   return GP_OK;
 }
 
@@ -1120,9 +1343,8 @@ int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const doub
     return GP_OK;
   }
 
-  // Fused one-pass adjoint.
-  const int KT = select_KT(c);
-  const int CK = 32 * KT;
+  // Fused one-pass adjoint, over groups of at most 256 columns (the sum over
+  // columns separates; one group holds 8 K-tiles of 32 columns).
   float* wf;
   CHK(ensure(ctx, B_SCALF, (size_t)kMaxC, &wf));
   CHK(ensure_pinned(ctx, kMaxC));
@@ -1131,49 +1353,54 @@ int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const doub
     for (int k = 0; k < c; ++k) hw[k] = (float)col_weights[k];
     HIPCHK(hipMemcpyAsync(wf, hw, c * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
   }
-  AdjArgs aa;
-  aa.prec = precision;
-  aa.D = px.D;
-  aa.xp = px.xp;
-  aa.n_pad = px.n_pad;
-  aa.KT = KT;
-  const size_t pc = (size_t)(px.n_pad * CK);
-  if (precision == GP_BF16X3) {
-    uint16_t *uh, *ul, *wh, *wl;
-    CHK(ensure(ctx, B_UHI, pc, &uh));
-    CHK(ensure(ctx, B_ULO, pc, &ul));
-    CHK(ensure(ctx, B_WHI, pc, &wh));
-    CHK(ensure(ctx, B_WLO, pc, &wl));
-    HIPCHK(pack_rows_bf16(U, n, ldu, c, wf, KT, uh, ul, px.n_pad, ctx->stream));
-    HIPCHK(pack_rows_bf16(W, n, ldw, c, nullptr, KT, wh, wl, px.n_pad, ctx->stream));
-    aa.uhi = uh; aa.ulo = ul; aa.whi = wh; aa.wlo = wl;
-  } else {
-    float *uf, *wf2;
-    CHK(ensure(ctx, B_UHI, pc * 2, (uint16_t**)&uf));
-    CHK(ensure(ctx, B_WHI, pc * 2, (uint16_t**)&wf2));
-    HIPCHK(pack_rows_f32(U, n, ldu, c, wf, KT, uf, px.n_pad, ctx->stream));
-    HIPCHK(pack_rows_f32(W, n, ldw, c, nullptr, KT, wf2, px.n_pad, ctx->stream));
-    aa.uhi = uf; aa.whi = wf2;
-  }
-  const int64_t rowblocks = px.n_pad / kAdjRowsPerWG;
-  aa.S = 1;
-  while (rowblocks * aa.S < 2048 && (px.n_pad / 16) / (2 * aa.S) >= 32) aa.S *= 2;
   const int nd = px.D + 1;
-  double* part;
-  CHK(ensure(ctx, B_ADJP, (size_t)(rowblocks * aa.S * nd), &part));
-  aa.partial = part;
-  int64_t rows = 0;
-  {
-    ProfScope ps(ctx, 1);
-    HIPCHK(adj(aa, &rows, ctx->stream));
-  }
-  CHK(ensure_pinned(ctx, (size_t)rows * nd));
-  HIPCHK(hipMemcpyAsync(ctx->hpin, part, rows * nd * sizeof(double), hipMemcpyDeviceToHost,
-                        ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
   std::vector<double> S(nd, 0.0);
-  for (int64_t r = 0; r < rows; ++r)
-    for (int k = 0; k < nd; ++k) S[k] += ctx->hpin[r * nd + k];
+  for (int g0 = 0; g0 < c; g0 += kAdjMaxCols) {
+    const int cg = std::min(kAdjMaxCols, c - g0);
+    const int KT = select_KT(cg);
+    const int CK = 32 * KT;
+    AdjArgs aa;
+    aa.prec = precision;
+    aa.D = px.D;
+    aa.xp = px.xp;
+    aa.n_pad = px.n_pad;
+    aa.KT = KT;
+    const size_t pc = (size_t)(px.n_pad * CK);
+    if (precision == GP_BF16X3) {
+      uint16_t *uh, *ul, *wh, *wl;
+      CHK(ensure(ctx, B_UHI, pc, &uh));
+      CHK(ensure(ctx, B_ULO, pc, &ul));
+      CHK(ensure(ctx, B_WHI, pc, &wh));
+      CHK(ensure(ctx, B_WLO, pc, &wl));
+      HIPCHK(pack_rows_bf16(U + g0, n, ldu, cg, wf + g0, KT, uh, ul, px.n_pad, ctx->stream));
+      HIPCHK(pack_rows_bf16(W + g0, n, ldw, cg, nullptr, KT, wh, wl, px.n_pad, ctx->stream));
+      aa.uhi = uh; aa.ulo = ul; aa.whi = wh; aa.wlo = wl;
+    } else {
+      float *uf, *wf2;
+      CHK(ensure(ctx, B_UHI, pc * 2, (uint16_t**)&uf));
+      CHK(ensure(ctx, B_WHI, pc * 2, (uint16_t**)&wf2));
+      HIPCHK(pack_rows_f32(U + g0, n, ldu, cg, wf + g0, KT, uf, px.n_pad, ctx->stream));
+      HIPCHK(pack_rows_f32(W + g0, n, ldw, cg, nullptr, KT, wf2, px.n_pad, ctx->stream));
+      aa.uhi = uf; aa.whi = wf2;
+    }
+    const int64_t rowblocks = px.n_pad / kAdjRowsPerWG;
+    aa.S = 1;
+    while (rowblocks * aa.S < 2048 && (px.n_pad / 16) / (2 * aa.S) >= 32) aa.S *= 2;
+    double* part;
+    CHK(ensure(ctx, B_ADJP, (size_t)(rowblocks * aa.S * nd), &part));
+    aa.partial = part;
+    int64_t rows = 0;
+    {
+      ProfScope ps(ctx, 1);
+      HIPCHK(adj(aa, &rows, ctx->stream));
+    }
+    CHK(ensure_pinned(ctx, (size_t)rows * nd));
+    HIPCHK(hipMemcpyAsync(ctx->hpin, part, rows * nd * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t r = 0; r < rows; ++r)
+      for (int k = 0; k < nd; ++k) S[k] += ctx->hpin[r * nd + k];
+  }
   for (int k = 0; k < d; ++k) grad_out[k] = a * a / (theta[k] * log2e * log2e) * S[k];
   grad_out[d] = 2.0 * a * S[px.D];
   return GP_OK;
@@ -1210,7 +1437,7 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
   std::memset(&s, 0, sizeof s);
   s.true_relres_y = s.true_relres_z = std::numeric_limits<double>::quiet_NaN();
   if (!cfg) return fail(ctx, GP_ERR_INVALID_ARG, "cfg is NULL");
-  CHK(check_dims(ctx, d, c));
+  CHK(check_dims(ctx, d, c, kMaxSolveC));
   CHK(check_theta(ctx, theta, d));
   CHK(check_prec(ctx, cfg->precision));
   CHK(check_mat(ctx, "X", X, n, d, d));
@@ -1328,7 +1555,7 @@ int gp_mll_grad(gp_ctx* ctx, const float* X, int64_t n, int d, const float* y,
   if (!grad_out) return fail(ctx, GP_ERR_INVALID_ARG, "grad_out is NULL");
   if (s < 1) return fail(ctx, GP_ERR_INVALID_ARG, "s = %d must be >= 1", s);
   const int c = s + 1;
-  CHK(check_dims(ctx, d, c));
+  CHK(check_dims(ctx, d, c, kMaxSolveC));
   CHK(check_theta(ctx, theta, d));
   CHK(check_mat(ctx, "X", X, n, d, d));
   CHK(check_mat(ctx, "y", y, n, 1, 1));
@@ -1412,6 +1639,19 @@ int gp_nu_to_theta(int p, const double* nu, int transform, double* theta) {
     const double v = nu[k];
     theta[k] = transform == GP_LOG ? std::exp(v)
                                    : (v > 0 ? v + std::log1p(std::exp(-v)) : std::log1p(std::exp(v)));
+  }
+  return GP_OK;
+}
+
+int gp_theta_to_nu(int p, const double* theta, int transform, double* nu) {
+  if (p < 0 || (p > 0 && (!nu || !theta))) return GP_ERR_INVALID_ARG;
+  if (transform != GP_SOFTPLUS && transform != GP_LOG) return GP_ERR_INVALID_ARG;
+  for (int k = 0; k < p; ++k)
+    if (!(theta[k] > 0.0) || !std::isfinite(theta[k])) return GP_ERR_INVALID_ARG;
+  for (int k = 0; k < p; ++k) {
+    const double t = theta[k];
+    // softplus^-1(t) = log(e^t - 1) = t + log(1 - e^-t)
+    nu[k] = transform == GP_LOG ? std::log(t) : t + std::log(-std::expm1(-t));
   }
   return GP_OK;
 }
@@ -1762,7 +2002,7 @@ int gp_init_heuristic(gp_ctx* ctx, const float* X, int64_t n, int d, const float
       l.g.resize(p);
       for (int k = 0; k < p; ++k) {
         const double t0 = cfg.theta0 ? cfg.theta0[k] : 1.0;
-        l.nu[k] = cfg.transform == GP_LOG ? std::log(t0) : t0 + std::log(-std::expm1(-t0));
+        gp_theta_to_nu(1, &t0, cfg.transform, &l.nu[k]);
       }
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));

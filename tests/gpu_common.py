@@ -49,3 +49,16 @@ def col_relerr(out, ref):
     num = np.linalg.norm(out - ref, axis=0)
     den = np.linalg.norm(ref, axis=0)
     return float(np.max(num / np.maximum(den, 1e-300)))
+
+
+def elem_relerr(out, ref):
+    """max |out - ref| over all entries / max |ref|: a few wrong entries (a tile
+    edge, a ragged tail) are not diluted by the rest of the column."""
+    return float(np.max(np.abs(out - ref)) / max(float(np.max(np.abs(ref))), 1e-300))
+
+
+def entry_bound_ratio(out, ref, mag):
+    """max over entries of |out - ref| / mag, where mag is the sum of the absolute
+    values of the terms that make up each entry (a deterministic rounding bound is
+    a multiple of it)."""
+    return float(np.max(np.abs(out - ref) / np.maximum(mag, 1e-300)))

@@ -45,6 +45,19 @@ def test_host_only_entry_points_without_gpu():
     th = np.zeros(3)
     assert L.gp_nu_to_theta(3, nu.ctypes.data_as(pd), N.GP_SOFTPLUS, th.ctypes.data_as(pd)) == 0
     np.testing.assert_allclose(th, np.log1p(np.exp(nu)), rtol=1e-14)
+    # the inverse: softplus(0) = log 2 and exp(0) = 1 map back to 0; round trips
+    back = np.zeros(3)
+    assert L.gp_theta_to_nu(3, th.ctypes.data_as(pd), N.GP_SOFTPLUS, back.ctypes.data_as(pd)) == 0
+    np.testing.assert_allclose(back, nu, rtol=1e-12, atol=1e-12)
+    two = np.array([np.log(2.0), 1.0])
+    z = np.ones(2)
+    assert L.gp_theta_to_nu(1, two.ctypes.data_as(pd), N.GP_SOFTPLUS, z.ctypes.data_as(pd)) == 0
+    assert abs(z[0]) < 1e-15
+    assert L.gp_theta_to_nu(1, two[1:].ctypes.data_as(pd), N.GP_LOG, z.ctypes.data_as(pd)) == 0
+    assert z[0] == 0.0
+    bad = np.array([0.5, -1.0])
+    assert L.gp_theta_to_nu(2, bad.ctypes.data_as(pd), N.GP_SOFTPLUS,
+                            z.ctypes.data_as(pd)) == N.GP_ERR_INVALID_ARG
     cfg = N.SolverCfg()
     L.gp_solver_cfg_default(C.byref(cfg))
     assert cfg.tol == 0.01 and cfg.ap_block == 1000 and cfg.sgd_batch == 500
@@ -106,7 +119,7 @@ def test_every_context_call_rejects_a_null_context():
                 for t in f.argtypes]
         assert f(*args) == N.GP_ERR_INVALID_ARG, name
         checked.append(name)
-    assert len(checked) == 12, checked
+    assert len(checked) == 14, checked
     assert L.gp_last_error(None) == b"null context"
     L.gp_ctx_destroy(None)
 
@@ -118,3 +131,32 @@ def test_missing_library_raises(monkeypatch, tmp_path):
     monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "libgpmi.so"))
     with pytest.raises(ImportError, match="no fallback"):
         N.lib()
+
+
+def test_workspace_size_without_a_device():
+    # host-only planning: grows with n and c, counts the preconditioner factor
+    # (rank 8000 at n = 434,874: about 14 GB of FP32 factor), rejects bad input
+    import ctypes as C
+    L = N.lib()
+    cfg = N.SolverCfg()
+    L.gp_solver_cfg_default(C.byref(cfg))
+    out = C.c_size_t()
+
+    def size(op, n, d, c, cf, M=0):
+        assert L.gp_workspace_size(op, n, d, c, C.byref(cf) if cf is not None else None, M,
+                                   C.byref(out)) == 0
+        return out.value
+
+    small = size(N.GP_WS_KMATVEC, 1000, 3, 65, None)
+    assert 0 < small < size(N.GP_WS_KMATVEC, 100_000, 3, 65, None)
+    plain = size(N.GP_WS_SOLVE, 434_874, 3, 65, cfg)
+    cfg.precond_rank = 8000
+    pc = size(N.GP_WS_SOLVE, 434_874, 3, 65, cfg)
+    assert pc - plain > 8000 * 434_874 * 4
+    assert size(N.GP_WS_MLL_GRAD, 434_874, 3, 65, cfg, 1000) > pc
+    assert size(N.GP_WS_SOLVE, 0, 3, 65, cfg) == 0
+    assert L.gp_workspace_size(7, 10, 3, 4, C.byref(cfg), 0, C.byref(out)) == N.GP_ERR_INVALID_ARG
+    assert L.gp_workspace_size(N.GP_WS_SOLVE, 10, 3, 4, None, 0, C.byref(out)) == N.GP_ERR_INVALID_ARG
+    assert L.gp_workspace_size(N.GP_WS_SOLVE, 10, 3, 300, C.byref(cfg), 0,
+                               C.byref(out)) == N.GP_ERR_INVALID_ARG
+    assert L.gp_workspace_size(N.GP_WS_KMATVEC, 10, 3, 4, None, 0, None) == N.GP_ERR_INVALID_ARG

@@ -1,19 +1,50 @@
 """Parity of the fused kernel-matrix product (gp_kmatvec) with the FP64 oracle.
 
 Tolerances:
-  FP32    1e-5   per column, ||out_c - ref_c|| / ||ref_c||  (target for the FP32 product)
-  BF16X3  2e-5   per column (bf16 hi/lo split of kernel values and V; ~2^-17 per entry)
-  BF16    3e-3   whole product, ||out - ref||_F / ||ref||_F (one bf16 rounding of both)
+  FP32    1e-5   per column, ||out_c - ref_c|| / ||ref_c||  (target for the FP32 product),
+                 and 2e-5 entry by entry, max |out - ref| / max |ref|
+  BF16X3  2e-5   per column and 4e-5 entry by entry (bf16 hi/lo split of kernel values
+                 and V; the dropped and rounded terms are at most 2^-16 of each term)
+                 The entry bound is twice the column bound: with squared distances from
+                 the FP32 norm expansion the error grows with a row's |x^|^2, so the
+                 rows of largest norm carry about 1.6x the typical error (an emulation
+                 of that arithmetic on the CPU reproduces the GPU's errors on the
+                 16,384-point workload: tests/test_tolerances.py).
+  BF16    3e-3   whole product, ||out - ref||_F / ||ref||_F: the RMS effect of one bf16
+                 rounding of each kernel value and each V entry.  It is a statistical
+                 bound that needs many terms per entry; a column of a few terms can
+                 exceed it (tests/test_tolerances.py measures both on the CPU).  Every
+                 entry also meets the deterministic bound of two roundings to 8
+                 significant bits, |out - ref| <= (2u + u^2) (a^2 K |V|) + 1e-4 (a^2 K |V|
+                 + sigma^2 |V|) with u = 2^-8 (the second term covers the FP32
+                 evaluation and accumulation).
 """
 import numpy as np
 import pytest
 
-from gpu_common import announce, col_relerr, dev, host, problem, require_gpu
+from gpu_common import announce, col_relerr, dev, elem_relerr, host, problem, require_gpu
 from oracle import kernel
 
 pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-5, 1: 2e-5, 2: 3e-3}
+BF16_U = 2.0 ** -8
+
+
+def check_product(out, ref, prec, mag_k=None, mag_noise=None):
+    """The tolerances of the module docstring.  mag_k = a^2 K |V| and mag_noise =
+    sigma^2 |V| (FP64) are needed for the BF16 entry bound."""
+    if prec == 2:
+        err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+        assert err <= TOL[2], err
+        mag_noise = 0.0 if mag_noise is None else mag_noise
+        bound = (2 * BF16_U + BF16_U ** 2) * mag_k + 1e-4 * (mag_k + mag_noise)
+        ratio = float(np.max(np.abs(out - ref) / np.maximum(bound, 1e-300)))
+        assert ratio <= 1.0, ratio
+        return err, ratio
+    col, ent = col_relerr(out, ref), elem_relerr(out, ref)
+    assert col <= TOL[prec] and ent <= 2 * TOL[prec], (col, ent)
+    return col, ent
 
 
 @pytest.fixture(scope="module")
@@ -50,13 +81,9 @@ def test_square_h_matvec(gp, n, d, c, dist, prec):
     announce("kmatvec", n, d, c, dist, prec)
     out = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=prec, add_noise=True))
     ref = kernel.h_matvec(X, theta, V)
-    if prec == 2:
-        # single bf16 rounding: the bound is on the whole product (few-term
-        # columns of tiny n do not average their rounding errors)
-        err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
-    else:
-        err = col_relerr(out, ref)
-    assert err <= TOL[prec], err
+    mag_k = kernel.k_matvec(X, X, theta, np.abs(V)) if prec == 2 else None
+    errs = check_product(out, ref, prec, mag_k, theta[-1] ** 2 * np.abs(V.astype(np.float64)))
+    print("[gpu-case] errors", n, d, c, prec, errs)
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
@@ -67,7 +94,7 @@ def test_rectangular_cross_product(gp, prec):
     announce("kmatvec-rect", prec)
     out = host(api.gp_kmatvec(gp, dev(Q), dev(X), theta, dev(V), precision=prec))
     ref = kernel.k_matvec(Q, X, theta, V)
-    assert col_relerr(out, ref) <= TOL[prec]
+    check_product(out, ref, prec)
 
 
 def test_leading_dimensions_and_column_subsets(gp):
@@ -81,7 +108,7 @@ def test_leading_dimensions_and_column_subsets(gp):
                    out=out[:, :40])
     o = host(out)
     assert np.all(o[:, 40:] == 123.0)
-    assert col_relerr(o[:, :40], kernel.h_matvec(X, theta, V)) <= 1e-5
+    check_product(o[:, :40], kernel.h_matvec(X, theta, V), 0)
 
 
 def test_empty_and_invalid(gp):
@@ -123,8 +150,7 @@ def test_full_size_precision_workload_sampled_rows(gp, prec):
     out = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V), precision=prec, add_noise=True))
     rows = np.random.default_rng(12).choice(w.n, 192, replace=False)
     ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
-    err = col_relerr(out[rows], ref)
-    assert err <= TOL[prec], err
+    print("[gpu-case] errors", check_product(out[rows], ref, prec))
 
 
 @pytest.mark.parametrize("prec", [1, 2], ids=["bf16x3", "bf16"])
@@ -147,11 +173,8 @@ def test_low_dimension_distance_forms(gp, prec, shift_rows, shift_cols):
     announce("kmatvec-xt", prec, shift_rows, shift_cols)
     out = host(api.gp_kmatvec(gp, dev(Q), dev(X), theta, dev(V), precision=prec))
     ref = kernel.k_matvec(Q, X, theta, V)
-    if prec == 2:
-        err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
-    else:
-        err = col_relerr(out, ref)
-    assert err <= TOL[prec], err
+    mag_k = kernel.k_matvec(Q, X, theta, np.abs(V)) if prec == 2 else None
+    print("[gpu-case] errors", check_product(out, ref, prec, mag_k))
 
 @pytest.mark.parametrize("name,prec", [("B", 0), ("B", 1), ("C", 1), ("E", 1)],
                          ids=["B-fp32", "B-bf16x3", "C-bf16x3", "E-bf16x3"])
@@ -179,5 +202,28 @@ def test_full_size_workloads_sampled_rows(gp, name, prec):
     rows = np.random.default_rng(14).choice(w.n, 96, replace=False)
     out = host(out_d[torch.from_numpy(rows).cuda()])
     ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
-    err = col_relerr(out, ref)
-    assert err <= TOL[prec], err
+    print("[gpu-case] errors", check_product(out, ref, prec))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
+def test_257_and_more_columns(gp, prec):
+    """s = 256 probes plus the mean column (Sec. 3, number of probe vectors): the
+    product runs in passes of at most 80 columns and the fused adjoint in passes of
+    at most 256, both up to 1024 columns; a solve takes at most 256 columns."""
+    from paper_2405_18457_amd import api
+    import torch
+    X, V, theta = problem(700, 3, 300, seed=257, dist="uniform", ell_scale=(0.2, 0.5))
+    announce("kmatvec-257", prec)
+    for c in (257, 300):
+        out = host(api.gp_kmatvec(gp, dev(X), dev(X), theta, dev(V[:, :c]), precision=prec,
+                                  add_noise=True))
+        check_product(out, kernel.h_matvec(X, theta, V[:, :c]), prec)
+    W = np.random.default_rng(258).standard_normal((700, 300)).astype(np.float32)
+    w = np.random.default_rng(259).uniform(-1, 1, 300)
+    g = api.gp_kmatvec_adjoint(gp, dev(X), theta, dev(V), dev(W), w, precision=prec)
+    ref = kernel.adjoint(X, theta, V, W, w)
+    assert np.max(np.abs(g - ref)) <= 2e-5 * np.max(np.abs(ref)), (g, ref)
+    with pytest.raises(api.GPError) as e:
+        api.gp_solve(gp, dev(X), theta, dev(V[:, :257]), torch.zeros((700, 257), device="cuda"),
+                     api.solver_cfg())
+    assert e.value.code == 1

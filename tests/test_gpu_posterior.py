@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_common import announce, dev, host, problem, require_gpu
+from gpu_common import announce, dev, elem_relerr, host, problem, require_gpu
 from oracle import mll, rff
 
 pytestmark = pytest.mark.gpu
@@ -41,7 +41,10 @@ def test_posterior_samples_match_oracle(gp, n, m, d, s, M, prec, tol):
                                      precision=prec))
     ref = rff.posterior_samples(Xq, X, theta, t, W, U[:, 0], U[:, 1:])
     err = float(np.linalg.norm(F - ref) / np.linalg.norm(ref))
-    assert err <= tol, err
+    ent = elem_relerr(F, ref)
+    print("[gpu-case] errors", err, ent)
+    # entries: twice the norm bound, as for the products (tests/test_gpu_kmatvec.py)
+    assert err <= tol and ent <= 2 * tol, (err, ent)
 
 
 def test_posterior_samples_edge_cases(gp):
@@ -78,6 +81,7 @@ def test_posterior_samples_from_a_pathwise_solve(gp):
     Uh = host(U)
     ref = rff.posterior_samples(Xq, X, theta, dr["t"], dr["W"], Uh[:, 0], Uh[:, 1:])
     assert float(np.linalg.norm(F - ref) / np.linalg.norm(ref)) <= 5e-5
+    assert elem_relerr(F, ref) <= 1e-4
     # the sample mean estimates the posterior mean k(Xq, X) H^-1 y (s = 16 samples)
     from oracle import kernel
     mu = kernel.k_matvec(Xq, X, theta, mll.exact_solve(X, theta, y[:, None].astype(np.float64)))[:, 0]

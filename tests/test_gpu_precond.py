@@ -7,7 +7,7 @@ import pytest
 
 import workloads as wl
 from gpu_common import announce, dev, host, problem, require_gpu
-from oracle import mll, precond, rff, solvers
+from oracle import kernel, mll, precond, rff, solvers
 
 pytestmark = pytest.mark.gpu
 
@@ -189,3 +189,74 @@ def test_reused_factor(gp, prec):
     assert s5["iterations"] <= 2 * s6["iterations"] + 5
     with pytest.raises(api.GPError):
         api.gp_solve(gp, Xd, theta, Bd, U6, api.solver_cfg(precond_rank=k, precond_reuse=-1))
+
+
+def test_full_size_precision_workload_solve_residual_rows(gp):
+    """Precision workload at full size (n = 434,874, d = 3, 65 columns) in the
+    configuration the bench times (bf16x3 products, rank-8000 pivoted-Cholesky
+    preconditioner): a cold solve at the data-generating theta, then a solve at a
+    moved theta (every hyperparameter moved by about one Adam step, lr 0.03)
+    warm-started from the first solution and reusing its factor.  On 192 sampled
+    rows the oracle recomputes B - H U in FP64 from the same U; the library's FP32
+    residual (its FP32 product) must agree entry by entry to the FP32 product's
+    accuracy, and the residual norms the library reports must agree with the
+    sampled-row estimate."""
+    import torch
+    from paper_2405_18457_amd import api
+    w = wl.WORKLOADS["D"]
+    X = wl.draw_inputs(w)
+    tr = wl.truth_draws(w)
+    md = wl.model_pathwise_draws(w)
+    theta = np.concatenate([tr["ell"], [1.0, w.sigma]])
+    Xd = dev(X)
+    announce("full-D rhs")
+    # right-hand sides of the pathwise system: targets from the data-generating
+    # random-feature draw, probes f(x) + sigma eps from the model's fixed features
+    y = api.gp_prior_sample(gp, Xd, theta, dev(tr["t"]), dev(tr["w"][:, None]))[:, 0]
+    y = y + w.sigma * dev(tr["noise"])
+    xi = api.gp_prior_sample(gp, Xd, theta, dev(md["t"]), dev(md["W"])) + w.sigma * dev(md["w_eps"])
+    Bd = torch.cat([y[:, None], xi], dim=1).contiguous()
+    U = torch.zeros_like(Bd)
+    announce("full-D cold solve")
+    s1 = api.gp_solve(gp, Xd, theta, Bd, U, api.solver_cfg(
+        tol=1e-2, precision=api.GP_BF16X3, precond_rank=8000, precond_reuse=1))
+    moved = theta * np.array([1.03, 0.97, 1.03, 0.97, 1.03])
+    announce("full-D warm solve")
+    s2 = api.gp_solve(gp, Xd, moved, Bd, U, api.solver_cfg(
+        tol=1e-2, precision=api.GP_BF16X3, precond_rank=8000, precond_reuse=1))
+    print(f"[gpu-case] cold {s1['iterations']} iterations, warm {s2['iterations']}", flush=True)
+    assert s1["converged"] and s2["converged"] and s2["iterations"] < s1["iterations"]
+    HU = api.gp_kmatvec(gp, Xd, Xd, moved, U, precision=api.GP_FP32, add_noise=True)
+    rows = np.sort(np.random.default_rng(16).choice(w.n, 192, replace=False))
+    ri = torch.from_numpy(rows).cuda()
+    R_lib = host((Bd - HU)[ri])
+    Uh = host(U)
+    HU_ref = (kernel.k_matvec(X[rows], X, moved, Uh) + moved[-1] ** 2 * Uh[rows])
+    R_ref = host(Bd[ri]) - HU_ref
+    # Entry by entry the FP32 residual inherits the FP32 product's rounding, which is
+    # relative to the magnitudes of the terms, S_i = a^2 sum_j k_ij |u_j| + sigma^2 |u_i|,
+    # not to the residual: the solution's components along small eigenvalues are
+    # large and cancel in H U.  Bound per entry: the squared-distance cancellation of
+    # the norm expansion, |d r^2| <= 3u (|x^_i|^2 + |x^_j|^2), moves the Matern value
+    # by at most (ln 2)^2 / 2 |d r^2| of itself, plus 64 units for the evaluation and
+    # the FP32 accumulation (u = 2^-24).
+    u32 = 2.0 ** -24
+    S = kernel.k_matvec(X[rows], X, moved, np.abs(Uh)) + moved[-1] ** 2 * np.abs(Uh[rows])
+    scl = np.sqrt(3.0) / np.log(2.0) / moved[:3]
+    nrm = ((X.astype(np.float64) * scl) ** 2).sum(1)
+    per_entry = (np.log(2.0) ** 2 / 2 * 3 * u32 * (nrm[rows] + nrm.max()) + 64 * u32)[:, None]
+    units = float(np.max(np.abs(R_lib - R_ref) / (per_entry * S)))
+    ent = float(np.max(np.abs(R_lib - R_ref)) / np.max(np.abs(R_ref)))
+    assert units <= 1.0, units
+    # norms: the library's true residual against the oracle's sampled-row estimate
+    nb = np.linalg.norm(host(Bd), axis=0)
+    est = np.sqrt(np.sum(R_ref ** 2, axis=0) * w.n / len(rows)) / nb
+    est_y, est_z = float(est[0]), float(np.mean(est[1:]))
+    print(f"[gpu-case] relres library ({s2['true_relres_y']:.4f}, {s2['true_relres_z']:.4f}), "
+          f"sampled oracle rows ({est_y:.4f}, {est_z:.4f}); entry error {ent:.2e} of max |R|, "
+          f"{units:.3f} of the per-entry bound", flush=True)
+    # 192 rows estimate a mean square to about 1/sqrt(192 / 2) = 10 % (chi-square), so
+    # 25 % on the norm of a single column and 10 % on the mean over 64 columns
+    assert abs(est_y - s2["true_relres_y"]) <= 0.25 * s2["true_relres_y"]
+    assert abs(est_z - s2["true_relres_z"]) <= 0.10 * s2["true_relres_z"]
+    assert est_z <= 1.1e-2

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from gpu_common import announce, dev, host, problem, require_gpu
+from fp32_emulation import iteration_band
 from oracle import kernel, solvers
 
 pytestmark = pytest.mark.gpu
@@ -49,12 +50,17 @@ def test_cg_reaches_tolerance(gp, n, d, c, sigma, prec):
     assert st["converged"] and ry <= 1.02e-2 and rz <= 1.02e-2, (st, ry, rz)
     Uo, so = solvers.cg(op, B, tol=1e-2)
     exact = np.linalg.solve(op.H, B.astype(np.float64))
-    # Same algorithm, different arithmetic: FP32 CG loses orthogonality sooner
-    # than FP64 CG on ill-conditioned systems and needs more iterations (a bf16x3
-    # solve may add one restart from the true residual).  Step-for-step
-    # agreement of the iterates is checked under a fixed budget below.
-    print("iterations gpu / oracle:", st["iterations"], so["iterations"], st)
-    assert 0.7 * so["iterations"] - 2 <= st["iterations"] <= 1.5 * so["iterations"] + 6, (st, so)
+    # Same algorithm, different arithmetic: CG with FP32 vectors loses
+    # orthogonality sooner than the FP64 oracle and needs 15-50 % more iterations
+    # on these systems.  The expected count is therefore that of the same
+    # recurrence run on the CPU with FP32 vectors, FP64 scalars and products whose
+    # entries carry errors of the precision's size, over several rounding
+    # patterns, widened by max(2, 10 %) (tests/fp32_emulation.py).  Step-for-step
+    # agreement with the oracle's iterates is checked under a fixed budget below.
+    its, lo, hi = iteration_band(op.H, B, 1e-2, prec)
+    print(f"[gpu-case] iterations gpu {st['iterations']}, oracle FP64 {so['iterations']}, "
+          f"FP32 emulation {its} -> [{lo:.1f}, {hi:.1f}]", flush=True)
+    assert lo <= st["iterations"] <= hi, (st, its)
     assert hnorm_err(op.H, Ug, exact) <= 3 * hnorm_err(op.H, Uo, exact) + 1e-4
 
 

@@ -55,3 +55,104 @@ def test_budgeted_cg_steps_are_insensitive_to_kernel_entry_errors():
     U1, _ = solvers.cg(_Dense(_perturbed(op.H, 2.0 ** -16, 1)), B, tol=1e-6, max_epochs=3)
     moved = float(np.abs(U1 - U0).max() / np.abs(U0).max())
     assert moved < 2e-4 / 10, moved
+
+
+from fp32_emulation import bf16_rne as _bf16_rne  # noqa: E402
+
+
+def test_bf16_rounding_meets_the_whole_product_bound_not_the_column_one():
+    # The shapes of test_square_h_matvec with exact bf16 rounding of every kernel
+    # value and every V entry (FP64 accumulation): the per-column relative error
+    # of such a product exceeds 3e-3 on most shapes (columns whose entries cancel),
+    # so 3e-3 is a statement about the whole product, where it holds; every entry
+    # meets the deterministic bound (2u + u^2) a^2 K|V| of two roundings, u = 2^-8.
+    from gpu_common import col_relerr
+    from oracle import kernel
+    from test_gpu_kmatvec import CASES
+    worst_col, worst_fro, worst_entry = 0.0, 0.0, 0.0
+    u = 2.0 ** -8
+    for n, d, c, dist in CASES:
+        X, V, theta = problem(n, d, c, seed=n * 7 + d + c, dist=dist)
+        K = kernel.kernel_matrix(X, X, theta[:d], 1.0)
+        a2, s2 = theta[d] ** 2, theta[d + 1] ** 2
+        V64 = V.astype(np.float64)
+        ref = a2 * K @ V64 + s2 * V64
+        Kb = _bf16_rne(K.astype(np.float32)).astype(np.float64)
+        Vb = _bf16_rne(V).astype(np.float64)
+        out = a2 * Kb @ Vb + s2 * V64
+        worst_col = max(worst_col, col_relerr(out, ref))
+        worst_fro = max(worst_fro, float(np.linalg.norm(out - ref) / np.linalg.norm(ref)))
+        bound = (2 * u + u * u) * a2 * K @ np.abs(V64)
+        worst_entry = max(worst_entry, float(np.max(np.abs(out - ref) / np.maximum(bound, 1e-300))))
+    assert worst_col > 3e-3, worst_col
+    assert worst_fro <= 3e-3, worst_fro
+    assert worst_entry <= 1.0, worst_entry
+
+
+def test_bf16x3_attainable_residual():
+    # The standard-estimator system of test_standard_estimator_parity (n = 600,
+    # sigma = 0.5): exact solves with operators whose entries carry relative
+    # errors of 2^-18 -- the size of the bf16x3 products' errors -- leave true
+    # relative residuals between 1e-5 and 1e-4, so a bf16x3 solve can reach
+    # tau = 1e-4 but not 1e-5, the tolerance of the FP32 case.
+    from fp32_emulation import attainable_relres
+    from oracle import kernel
+    X, _, theta = problem(600, 3, 1, seed=21, sigma=0.5)
+    g = np.random.default_rng(22)
+    y = g.standard_normal(600)
+    Z = g.standard_normal((600, 16))
+    H = kernel.h_matrix(X, theta)
+    floor = attainable_relres(H, np.concatenate([y[:, None], Z], axis=1), 2.0 ** -18)
+    assert 1e-5 < floor.max() < 1e-4, floor
+
+
+def test_fp32_cg_needs_more_iterations_than_fp64():
+    # CG with FP32 vectors and FP64 scalars (the library's split) on the most
+    # ill-conditioned system of test_cg_reaches_tolerance takes far more
+    # iterations than the FP64 oracle -- beyond max(2, 10 %) of the oracle's count
+    # -- which is why the GPU count is compared with this emulation, not with the
+    # oracle's count.
+    from fp32_emulation import iteration_band
+    from oracle import solvers
+    X, B, theta = problem(700, 3, 17, seed=717, dist="uniform", sigma=0.1, ell_scale=(0.2, 0.5))
+    op = solvers.DenseOperator(X, theta)
+    _, so = solvers.cg(op, B, tol=1e-2)
+    its, lo, hi = iteration_band(op.H, B, 1e-2, 0)
+    assert min(its) > so["iterations"] + max(2, 0.1 * so["iterations"]), (its, so["iterations"])
+
+
+def test_cross_term_distances_concentrate_the_error_in_large_norm_rows():
+    # The 16,384-point workload at its data-generating theta, 96 sampled rows, 65
+    # columns: squared distances from the FP32 norm expansion (as the GPU forms
+    # them on its matrix cores), the Matern value and its bf16 hi/lo split, the
+    # three bf16 products accumulated exactly.  The column error stays inside the
+    # 2e-5 bf16x3 bound, while the largest entry error is about 1.6x the column
+    # error (rows of large |x^|^2), inside the 4e-5 entry bound.  The GPU measured
+    # 1.44e-5 and 2.24e-5 on these rows.
+    import workloads as wl
+    from gpu_common import col_relerr, elem_relerr
+    from oracle import kernel
+    w = wl.WORKLOADS["B"]
+    X = wl.draw_inputs(w)
+    ell = wl.draw_true_lengthscales(w)
+    theta = np.concatenate([ell, [1.0, w.sigma]])
+    V = wl.draw_normal(np.random.default_rng(13), (w.n, 65))
+    rows = np.random.default_rng(14).choice(w.n, 96, replace=False)
+    ref = kernel.k_matvec(X[rows], X, theta, V) + w.sigma ** 2 * V[rows].astype(np.float64)
+    sc = (np.float32(np.sqrt(3.0) * np.log2(np.e)) / ell.astype(np.float32)).astype(np.float32)
+    Xh = (X * sc).astype(np.float32)
+    nrm = np.sum(Xh * Xh, axis=1, dtype=np.float32)
+    cross = (Xh[rows] @ Xh.T).astype(np.float32)
+    r2 = np.abs(nrm[rows, None] + nrm[None, :] - np.float32(2) * cross).astype(np.float32)
+    rho = np.sqrt(r2).astype(np.float64)
+    m = ((1 + np.log(2) * rho) * np.exp2(-rho)).astype(np.float32)
+    hi = _bf16_rne(m)
+    lo = _bf16_rne(m - hi)
+    Vf = V.astype(np.float32)
+    vh = _bf16_rne(Vf)
+    vl = _bf16_rne(Vf - vh)
+    H, L, Vh, Vl = (a.astype(np.float64) for a in (hi, lo, vh, vl))
+    out = H @ Vh + H @ Vl + L @ Vh + w.sigma ** 2 * V[rows].astype(np.float64)
+    col, ent = col_relerr(out, ref), elem_relerr(out, ref)
+    assert 1e-5 < col <= 2e-5, col
+    assert 1.3 * col < ent <= 4e-5, (col, ent)
