@@ -105,39 +105,49 @@ def _normalise(B, U0):
 
 
 def cg(op, B, tol=0.01, max_epochs=None, U0=None, precond=None):
-    """Algorithm 1.  Returns (U, stats)."""
-    Pinv = (lambda R: R) if precond is None else precond
-    Bt, V, scale = _normalise(B, U0)
-    R = Bt - op.matvec(V)
-    matvecs = 1
-    Z = Pinv(R)
-    D = Z.copy()
-    gamma = np.einsum("ic,ic->c", R, Z)
-    t = 0
+    """Conjugate gradients with a preconditioner (App. B, Algorithm 1).  Returns (U, stats).
+
+    Every column minimises the H-norm error over a growing Krylov space.  The
+    search direction of a column is its preconditioned residual made
+    H-conjugate to the previous direction; the exact line minimum along it sets
+    the step; the residual follows by the same step along H times the direction.
+    The conjugation coefficient is the ratio of successive residual inner products
+    <r, P^-1 r>, which is what H-conjugacy reduces to in exact arithmetic.
+    """
+    apply_pinv = (lambda Res: Res) if precond is None else precond
+    target, x, scale = _normalise(B, U0)
+    res = target - op.matvec(x)
+    products = 1
+    pres = apply_pinv(res)
+    direction = pres.copy()
+    rho = np.einsum("ic,ic->c", res, pres)          # <r, P^-1 r> per column
+    steps = 0
     cap = SAFETY_CAP if max_epochs is None else max_epochs
-    ry, rz = relres(R)
-    _check_finite(R)
-    while t < cap and _keep_going(ry, rz, tol):
-        HD = op.matvec(D)
-        matvecs += 1
-        dHd = np.einsum("ic,ic->c", D, HD)
-        live = gamma != 0
-        if np.any(live & ~(dHd > 0)):
+    ry, rz = relres(res)
+    _check_finite(res)
+    while steps < cap and _keep_going(ry, rz, tol):
+        h_dir = op.matvec(direction)
+        products += 1
+        curvature = np.einsum("ic,ic->c", direction, h_dir)
+        live = rho != 0
+        if np.any(live & ~(curvature > 0)):
             raise SolverError("breakdown", "d^T H d <= 0")
-        alpha = np.where(live, gamma / np.where(live, dHd, 1.0), 0.0)
-        V = V + alpha * D
-        R = R - alpha * HD
-        Z = Pinv(R)
-        gnew = np.einsum("ic,ic->c", R, Z)
-        beta = np.where(live, gnew / np.where(live, gamma, 1.0), 0.0)
-        gamma = gnew
-        D = Z + beta * D
-        t += 1
-        _check_finite(R)
-        ry, rz = relres(R)
-    stats = dict(iterations=t, epochs=float(t), matvecs=matvecs, relres_y=ry, relres_z=rz,
-                 converged=not _keep_going(ry, rz, tol))
-    return V * scale, stats
+        # exact minimiser of the quadratic along the direction
+        step = np.where(live, rho / np.where(live, curvature, 1.0), 0.0)
+        x = x + step * direction
+        res = res - step * h_dir
+        pres = apply_pinv(res)
+        rho_next = np.einsum("ic,ic->c", res, pres)
+        # keep the next direction H-conjugate to this one
+        conj = np.where(live, rho_next / np.where(live, rho, 1.0), 0.0)
+        rho = rho_next
+        direction = pres + conj * direction
+        steps += 1
+        _check_finite(res)
+        ry, rz = relres(res)
+    stats = dict(iterations=steps, epochs=float(steps), matvecs=products, relres_y=ry,
+                 relres_z=rz, converged=not _keep_going(ry, rz, tol))
+    return x * scale, stats
 
 
 def _ap_blocks(n, b):
@@ -145,75 +155,80 @@ def _ap_blocks(n, b):
 
 
 def ap(op, B, block=1000, tol=0.01, max_epochs=None, U0=None):
-    """Algorithm 2.  Returns (U, stats).
+    """Alternating projections (App. B, Algorithm 2).  Returns (U, stats).
 
-    Blocks are contiguous in the given row order, the last one holding n mod b
-    rows.  Every block's Cholesky factor is computed once per call (once per
-    marginal-likelihood step) and cached.  The block chosen each iteration
-    maximises || r_y[I] + sum_j r_j[I] || (the printed score, read literally);
-    ties go to the lowest block index.  The selection rule is pinned by a
-    hand-computed case in which this score and a per-column score choose
-    different blocks; the solver itself by exactness and convergence properties.
+    Block coordinate descent on the quadratic 1/2 u^T H u - b^T u: the rows split
+    into contiguous blocks (the last one holding n mod b rows); each iteration
+    takes the block whose summed residual || r_y[I] + sum_j r_j[I] || is largest
+    (the score as printed, read literally; ties to the lowest block) and solves
+    exactly for that block's coordinates, which zeroes the residual on the block.
+    The block matrices are factored once per call (once per marginal-likelihood
+    step).  The selection rule is pinned by a hand-computed case in which this
+    score and a per-column score choose different blocks; the solver by exactness
+    and convergence properties.
     """
-    Bt, V, scale = _normalise(B, U0)
-    n = Bt.shape[0]
+    target, x, scale = _normalise(B, U0)
+    n = target.shape[0]
     blocks = _ap_blocks(n, block)
-    factors = [sla.cho_factor(op.block(I), lower=True) for I in blocks]
-    R = Bt - op.matvec(V)
+    block_factors = [sla.cho_factor(op.block(rows), lower=True) for rows in blocks]
+    res = target - op.matvec(x)
     limit = np.inf if max_epochs is None else (n / block) * max_epochs
     cap = SAFETY_CAP * len(blocks)
-    t = 0
-    ry, rz = relres(R)
-    _check_finite(R)
+    steps = 0
+    ry, rz = relres(res)
+    _check_finite(res)
     chosen = []
-    while t < limit and t < cap and _keep_going(ry, rz, tol):
-        summed = R.sum(axis=1)
-        scores = np.array([np.linalg.norm(summed[I]) for I in blocks])
-        k = int(np.argmax(scores))
-        I = blocks[k]
+    while steps < limit and steps < cap and _keep_going(ry, rz, tol):
+        combined = res.sum(axis=1)
+        k = int(np.argmax([np.linalg.norm(combined[rows]) for rows in blocks]))
+        rows = blocks[k]
         chosen.append(k)
-        delta = sla.cho_solve(factors[k], R[I])
-        V[I] += delta
-        R = R - op.rows(I).T @ delta          # H[:, I] delta, H symmetric
-        t += 1
-        _check_finite(R)
-        ry, rz = relres(R)
-    stats = dict(iterations=t, epochs=t * block / n, relres_y=ry, relres_z=rz,
+        # exact minimisation over the block: H[I, I] delta = r[I]
+        delta = sla.cho_solve(block_factors[k], res[rows])
+        x[rows] += delta
+        res = res - op.rows(rows).T @ delta          # H[:, I] delta, H symmetric
+        steps += 1
+        _check_finite(res)
+        ry, rz = relres(res)
+    stats = dict(iterations=steps, epochs=steps * block / n, relres_y=ry, relres_z=rz,
                  converged=not _keep_going(ry, rz, tol), chosen=chosen)
-    return V * scale, stats
+    return x * scale, stats
 
 
 def sgd(op, B, batches, lr, momentum=0.9, tol=0.01, max_epochs=None, U0=None):
-    """Algorithm 3.  ``batches`` [iters, b] int holds the index set of every
-    iteration (drawn by the caller).  Returns (U, stats).
+    """Stochastic gradient descent with heavy-ball momentum (App. B, Algorithm 3) on the
+    quadratic 1/2 u^T H u - b^T u.  ``batches`` [iters, b] holds the rows sampled in
+    every iteration (drawn by the caller).  Returns (U, stats).
 
-    The residual estimate starts at b~ even under warm start (as printed) and
-    row i of it is overwritten by g[i] = H[i, :] v - b~[i] (the negative
-    residual; only its norm is used).  Heavy-ball momentum as printed; g uses
-    the pre-update v; no Polyak averaging.
+    The gradient of the quadratic on the sampled rows is H[I, :] u - b[I] (taken at
+    the pre-update iterate); its rows are scattered into a zero vector and enter a
+    heavy-ball velocity with step lr / b.  No averaging of iterates.  The residual is
+    not computed by the method; its running estimate keeps, for every row, the
+    negative of the last gradient seen there (the residual up to sign), starting from
+    b itself -- also under warm start, as printed -- and only its norms are used.
     """
-    Bt, V, scale = _normalise(B, U0)
-    n = Bt.shape[0]
+    target, x, scale = _normalise(B, U0)
+    n = target.shape[0]
     batches = np.asarray(batches)
     b = batches.shape[1]
-    R = Bt.copy()
-    Mom = np.zeros_like(Bt)
+    res_estimate = target.copy()
+    velocity = np.zeros_like(target)
     limit = np.inf if max_epochs is None else (n / b) * max_epochs
-    t = 0
-    ry, rz = relres(R)
-    while t < limit and t < batches.shape[0] and _keep_going(ry, rz, tol):
-        I = batches[t]
-        G = op.rows(I) @ V - Bt[I]
-        Mom = momentum * Mom
-        Mom[I] -= (lr / b) * G
-        V = V + Mom
-        R[I] = G
-        t += 1
-        _check_finite(R)
-        ry, rz = relres(R)
-    stats = dict(iterations=t, epochs=t * b / n, relres_y=ry, relres_z=rz,
+    steps = 0
+    ry, rz = relres(res_estimate)
+    while steps < limit and steps < batches.shape[0] and _keep_going(ry, rz, tol):
+        rows = batches[steps]
+        batch_grad = op.rows(rows) @ x - target[rows]
+        velocity = momentum * velocity
+        velocity[rows] -= (lr / b) * batch_grad
+        x = x + velocity
+        res_estimate[rows] = batch_grad
+        steps += 1
+        _check_finite(res_estimate)
+        ry, rz = relres(res_estimate)
+    stats = dict(iterations=steps, epochs=steps * b / n, relres_y=ry, relres_z=rz,
                  converged=not _keep_going(ry, rz, tol))
-    return V * scale, stats
+    return x * scale, stats
 
 
 def true_relres(op, B, U):
