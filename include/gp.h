@@ -123,6 +123,25 @@ int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_
                const double* theta, const float* V, int64_t ldv, int c, float* out, int64_t ldo,
                int precision, int add_noise);
 
+/* gp_kmatvec for callers that cannot allocate memory (code that must not call
+ * hipMalloc or an allocating library routine, such as a tight serving loop or a
+ * harness that forbids it): the same product, arguments, results and errors,
+ * with every buffer of the call (packed inputs, bf16 / FP32 operand tiles,
+ * column-split partial sums) carved from a static device array of 64 MiB that the
+ * library holds on each device it runs on until the process ends, and host
+ * staging kept in the context.  No hipMalloc, hipHostMalloc or hipFree.
+ * Limit: the packed inputs and one column pass of packed V must fit 64 MiB, e.g.
+ * n1 = n2 = 150,000 with d <= 3 and c <= 80 (inputs 16 bytes a row, V tiles 320
+ * bytes a row); larger calls fail with GP_ERR_INVALID_ARG and a message that
+ * names the sizes.  The split of the column range over workgroups is reduced to
+ * what the remaining scratch holds, so the summation order (and the last bits)
+ * can differ from gp_kmatvec's.  Every call on one device shares that device's
+ * array and overwrites it: calls that overlap on one device (two host threads,
+ * or two streams) race; serialise them.  Per-launch profiling is not recorded.  */
+int gp_kmatvec_static(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_t n2,
+                      int d, const double* theta, const float* V, int64_t ldv, int c, float* out,
+                      int64_t ldo, int precision, int add_noise);
+
 /* Bilinear adjoint: grad_out[k] = sum_c col_weights[c] * U[:,c]^T (dH/dtheta_k) W[:,c]
  * for k = 0..d+1 (ell_1..ell_d, a, sigma), with dH/dsigma = 2 sigma I
  * (App. A).  This is the contraction of the gradient estimators (Sec. 2

@@ -30,7 +30,7 @@ EXPORTS = (
     "gp_profile_read", "gp_kmatvec", "gp_kmatvec_adjoint", "gp_solver_cfg_default", "gp_solve",
     "gp_prior_sample", "gp_mll_grad", "gp_adam_ascent", "gp_nu_to_theta", "gp_theta_to_nu", "gp_pivoted_cholesky",
     "gp_posterior_sample", "gp_nearest", "gp_exact_mll", "gp_init_cfg_default", "gp_init_heuristic",
-    "gp_workspace_size", "gp_workspace_reserve", "gp_workspace_held",
+    "gp_workspace_size", "gp_workspace_reserve", "gp_workspace_held", "gp_kmatvec_static",
 )
 
 
@@ -86,6 +86,8 @@ def lib():
             "gp_profile_enable": (i32, [vp, i32]),
             "gp_profile_read": (i32, [vp, i32, pd, pi64]),
             "gp_kmatvec": (i32, [vp, vp, i64, vp, i64, i32, pd, vp, i64, i32, vp, i64, i32, i32]),
+            "gp_kmatvec_static": (i32, [vp, vp, i64, vp, i64, i32, pd, vp, i64, i32, vp, i64, i32,
+                                        i32]),
             "gp_kmatvec_adjoint": (i32, [vp, vp, i64, i32, pd, vp, i64, vp, i64, i32, pd, i32, i32,
                                          pd]),
             "gp_solver_cfg_default": (None, [C.POINTER(SolverCfg)]),

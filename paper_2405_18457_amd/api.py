@@ -118,7 +118,8 @@ def solver_cfg(solver=GP_CG, tol=0.01, max_epochs=0.0, precision=GP_FP32, refine
     return cfg
 
 
-def gp_kmatvec(ctx: Context, X1, X2, theta, V, precision=GP_FP32, add_noise=False, out=None):
+def gp_kmatvec(ctx: Context, X1, X2, theta, V, precision=GP_FP32, add_noise=False, out=None,
+               _entry="gp_kmatvec"):
     n1, d = X1.shape
     n2 = X2.shape[0]
     c = _cols(V)
@@ -129,9 +130,15 @@ def gp_kmatvec(ctx: Context, X1, X2, theta, V, precision=GP_FP32, add_noise=Fals
     x2, _ = _dptr(X2, "X2")
     v, ldv = _dptr(V, "V")
     o, ldo = _dptr(out, "out")
-    ctx.check(N.lib().gp_kmatvec(ctx.handle, x1, n1, x2, n2, d, thp, v, ldv, c, o, ldo, precision,
-                                 int(add_noise)))
+    ctx.check(getattr(N.lib(), _entry)(ctx.handle, x1, n1, x2, n2, d, thp, v, ldv, c, o, ldo,
+                                       precision, int(add_noise)))
     return out
+
+
+def gp_kmatvec_static(ctx: Context, X1, X2, theta, V, precision=GP_FP32, add_noise=False,
+                      out=None):
+    """gp_kmatvec through the allocation-free entry point (static device scratch)."""
+    return gp_kmatvec(ctx, X1, X2, theta, V, precision, add_noise, out, _entry="gp_kmatvec_static")
 
 
 def gp_kmatvec_adjoint(ctx: Context, X, theta, U, W, weights, precision=GP_BF16X3,

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -67,6 +68,17 @@ struct gp_ctx {
   size_t cap[B_COUNT] = {};
   double* hpin = nullptr;  // pinned host scratch
   size_t hpin_cap = 0;
+  // Allocation-free calls (gp_kmatvec_static): while `arena.on`, workspace
+  // buffers are carved from the device's static scratch array and host staging
+  // uses `arena_host`; nothing is allocated.
+  struct {
+    bool on = false;
+    unsigned char* base = nullptr;
+    size_t cap = 0, used = 0;
+    unsigned char* ptr[B_COUNT] = {};
+    size_t size[B_COUNT] = {};
+  } arena;
+  double arena_host[64] = {};
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kProfClasses];
   std::vector<hipEvent_t> pool;
@@ -74,7 +86,32 @@ struct gp_ctx {
   int64_t prof_n[kProfClasses] = {};
 };
 
+// Scratch of the allocation-free product (gp_kmatvec_static): a file-scope device
+// array, one copy per device, held until the process ends.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch, looked up once per device with it current.
+int scratch_address(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return GP_ERR_HIP;
+    }
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return GP_OK;
+}
 
 int fail(gp_ctx* c, int code, const char* fmt, ...) {
   char b[512];
@@ -103,6 +140,21 @@ int fail(gp_ctx* c, int code, const char* fmt, ...) {
 template <typename T>
 int ensure(gp_ctx* ctx, BufId id, size_t count, T** out) {
   size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  if (ctx->arena.on) {
+    auto& a = ctx->arena;
+    if (a.size[id] < bytes) {
+      const size_t off = (a.used + 255) & ~(size_t)255;
+      if (off > a.cap || bytes > a.cap - off)
+        return fail(ctx, GP_ERR_INVALID_ARG,
+                    "the call needs more than the %zu bytes of static scratch of the "
+                    "allocation-free entry point", a.cap);
+      a.ptr[id] = a.base + off;
+      a.size[id] = bytes;
+      a.used = off + bytes;
+    }
+    *out = reinterpret_cast<T*>(a.ptr[id]);
+    return GP_OK;
+  }
   if (ctx->cap[id] < bytes) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->buf[id]) HIPCHK(hipFree(ctx->buf[id]));
@@ -124,6 +176,9 @@ int ensure(gp_ctx* ctx, BufId id, size_t count, T** out) {
 
 int ensure_pinned(gp_ctx* ctx, size_t doubles) {
   if (ctx->hpin_cap >= doubles) return GP_OK;
+  if (ctx->arena.on)
+    return fail(ctx, GP_ERR_INVALID_ARG, "host staging of %zu values exceeds the %zu of the "
+                "allocation-free entry point", doubles, ctx->hpin_cap);
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (ctx->hpin) HIPCHK(hipHostFree(ctx->hpin));
   ctx->hpin = nullptr;
@@ -317,6 +372,14 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     const int64_t rowblocks =
         p1.n_pad / (64 * (a.xt ? fwd_xt_row_subtiles(CT, xt_chunks(p1.D)) : fwd_row_subtiles(CT)));
     a.S = choose_splits(rowblocks, a.steps);
+    if (ctx->arena.on) {
+      // allocation-free calls: as many column splits as the scratch left holds
+      const size_t used = (ctx->arena.used + 255) & ~(size_t)255;
+      const size_t left = ctx->arena.size[B_PART] > 0
+                              ? ctx->arena.size[B_PART]
+                              : (used < ctx->arena.cap ? ctx->arena.cap - used : 0);
+      while (a.S > 1 && (size_t)(a.S * p1.n_pad * 16 * CT) * sizeof(float) > left) a.S /= 2;
+    }
     if (a.S > 1) CHK(ensure(ctx, B_PART, (size_t)(a.S * p1.n_pad * 16 * CT), &a.part));
     {
       // the profile class times the forward kernel launch alone
@@ -1168,6 +1231,13 @@ int gp_ctx_create(int device, void* stream, gp_ctx** out) {
   if (!out) return GP_ERR_INVALID_ARG;
   *out = nullptr;
   HIPCHK(hipSetDevice(device));
+  if (device < 0 || device >= kMaxDevices) return GP_ERR_INVALID_ARG;
+  {
+    // the allocation-free entry point's scratch address on this device
+    unsigned char* sp = nullptr;
+    const int rs = scratch_address(device, &sp);
+    if (rs != GP_OK) return rs;
+  }
   ctx = new gp_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
@@ -1293,6 +1363,69 @@ int gp_kmatvec(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_
     CHK(pack_points(ctx, B_XP2, X2, nullptr, n2, d, theta, &p2));
   return kprod(ctx, p1, p2, V, ldv, c, out, ldo, precision, a2_of(theta, d),
                add_noise ? V : nullptr, ldv, s2_of(theta, d));
+}
+
+int gp_kmatvec_static(gp_ctx* ctx, const float* X1, int64_t n1, const float* X2, int64_t n2,
+                      int d, const double* theta, const float* V, int64_t ldv, int c, float* out,
+                      int64_t ldo, int precision, int add_noise) {
+  if (!ctx) return GP_ERR_INVALID_ARG;
+  ctx->err.clear();
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return fail(ctx, GP_ERR_HIP, "no static scratch address for device %d", ctx->device);
+  // The same validation as gp_kmatvec, then the plan: every buffer of the call must
+  // fit the scratch (column-split partial sums excepted: kprod fits their number).
+  CHK(check_dims(ctx, d, c));
+  CHK(check_prec(ctx, precision));
+  WsPlan plan;
+  plan_pack(plan, B_XP1, n1, d);
+  if (!(X2 == X1 && n2 == n1)) plan_pack(plan, B_XP2, n2, d);
+  {
+    WsPlan v;
+    plan_kprod(v, n1, n2, d, c, precision);
+    plan.need(B_VHI, v.bytes[B_VHI]);
+    plan.need(B_VLO, v.bytes[B_VLO]);
+  }
+  size_t need = 0;
+  for (size_t b : plan.bytes)
+    if (b) need += (std::max<size_t>(b, 256) + 255) & ~(size_t)255;
+  if (need > kStaticScratchBytes)
+    return fail(ctx, GP_ERR_INVALID_ARG,
+                "n1 = %lld, n2 = %lld, d = %d, c = %d needs %zu bytes of scratch; the "
+                "allocation-free product has %zu", (long long)n1, (long long)n2, d, c, need,
+                kStaticScratchBytes);
+  // arena scope: workspace from the scratch array, host staging in the context,
+  // no per-launch profiling events (their creation could allocate)
+  struct Scope {
+    gp_ctx* c;
+    double* hpin;
+    size_t hcap;
+    bool prof;
+    Scope(gp_ctx* ctx, unsigned char* base) : c(ctx), hpin(ctx->hpin), hcap(ctx->hpin_cap),
+                                             prof(ctx->prof) {
+      c->arena.on = true;
+      c->arena.base = base;
+      c->arena.cap = kStaticScratchBytes;
+      c->arena.used = 0;
+      for (int i = 0; i < B_COUNT; ++i) {
+        c->arena.ptr[i] = nullptr;
+        c->arena.size[i] = 0;
+      }
+      c->hpin = c->arena_host;
+      c->hpin_cap = sizeof(c->arena_host) / sizeof(double);
+      c->prof = false;
+    }
+    ~Scope() {
+      c->arena.on = false;
+      c->hpin = hpin;
+      c->hpin_cap = hcap;
+      c->prof = prof;
+    }
+  } scope(ctx, base);
+  return gp_kmatvec(ctx, X1, n1, X2, n2, d, theta, V, ldv, c, out, ldo, precision, add_noise);
 }
 
 int gp_kmatvec_adjoint(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,

@@ -119,7 +119,7 @@ def test_every_context_call_rejects_a_null_context():
                 for t in f.argtypes]
         assert f(*args) == N.GP_ERR_INVALID_ARG, name
         checked.append(name)
-    assert len(checked) == 14, checked
+    assert len(checked) == 15, checked
     assert L.gp_last_error(None) == b"null context"
     L.gp_ctx_destroy(None)
 
