@@ -93,6 +93,10 @@ def parse():
     ap.add_argument("--probe-scaling", action="store_true",
                     help="only time the forward product at 1..256 columns on the bench inputs "
                          "(cost of adding probe vectors)")
+    ap.add_argument("--theta0", choices=["true", "heuristic"], default="true",
+                    help="starting hyperparameters of the timed run: the data-generating theta, "
+                         "or the initial-hyperparameter heuristic of the large data sets "
+                         "(App. B; computed before the timed region and reported)")
     ap.add_argument("--init-heuristic", action="store_true",
                     help="time the initial-hyperparameter heuristic instead (own JSON line)")
     ap.add_argument("--init-centres", type=int, default=10)
@@ -100,6 +104,15 @@ def parse():
     ap.add_argument("--init-m", type=int, default=10_000)
     ap.add_argument("--init-single", type=int, default=10,
                     help="single evaluations timed for the roofline of the heuristic line")
+    ap.add_argument("--early-stop", action="store_true",
+                    help="the early-stopping workload instead (n = 2,049,280, d = 11): pathwise "
+                         "steps with a budget of 10 solver epochs each, warm-started and cold, "
+                         "true relative residual of every budgeted solution (own JSON line)")
+    ap.add_argument("--es-steps", type=int, default=3, help="steps per leg of --early-stop")
+    ap.add_argument("--es-epochs", type=float, default=10.0)
+    ap.add_argument("--es-solver", choices=["cg", "ap", "sgd"], default="cg")
+    ap.add_argument("--es-rank", type=int, default=100,
+                    help="pivoted-Cholesky rank of --early-stop (the paper's CG uses 100)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler against a known traffic)")
@@ -236,6 +249,70 @@ def init_heuristic(args):
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline_exact(inp["Xh"], y.cpu().numpy(), int(centres[0]), m)
+    print(json.dumps(rec), flush=True)
+
+
+def early_stop(args):
+    """Early stopping at scale (Sec. 5 "The Effects of Early Stopping"; App. B: a budget
+    of 10 solver epochs per outer step on the large data sets): the pathwise estimator
+    with CG stopped after `--es-epochs` epochs, once warm-started from the previous
+    step's solution and once from zero, each for `--es-steps` Adam steps (lr 0.03) from
+    the data-generating theta.  Reports every budgeted solution's FP32 true relative
+    residual (mean and probe criteria), whose average over the steps is the paper's
+    comparison (Tables 8-11), and the step times."""
+    import torch
+    import workloads as wl
+    from paper_2405_18457_amd import api
+    torch.cuda.init()
+    ctx = api.Context(0)
+    w = wl.WORKLOADS["E"]
+    n = w.n if args.n is None else args.n
+    X = wl.draw_inputs(w, n=n)
+    tr = wl.truth_draws(w, n=n)
+    md = wl.model_pathwise_draws(w, n=n)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    inp = {"w": w, "n": n, "X": dev(X), "t": dev(md["t"]), "W": dev(md["W"]),
+           "w_eps": dev(md["w_eps"]),
+           "theta_true": np.concatenate([tr["ell"], [1.0, w.sigma]])}
+    y = build_targets(ctx, inp, tr, dev)
+    torch.cuda.synchronize()
+    legs = {}
+    for leg in ("warm", "cold"):
+        solver = {"cg": api.GP_CG, "ap": api.GP_AP, "sgd": api.GP_SGD}[args.es_solver]
+        cfg = api.solver_cfg(solver=solver, tol=1e-2, max_epochs=args.es_epochs,
+                             precision=api.GP_BF16X3,
+                             precond_rank=args.es_rank if solver == api.GP_CG else 0,
+                             ap_block=1000, sgd_batch=500, sgd_lr=50.0, sgd_momentum=0.9,
+                             sgd_seed=8)
+        trn = api.Trainer(ctx, inp["X"], y, inp["theta_true"], api.GP_PATHWISE, cfg, lr=0.03,
+                          s=w.s, transform=api.GP_SOFTPLUS, warm=leg == "warm", rff_t=inp["t"],
+                          rff_W=inp["W"], w_eps=inp["w_eps"])
+        log = []
+        for k in range(args.es_steps):
+            t0 = time.perf_counter()
+            th, _, st = trn.step()
+            torch.cuda.synchronize()
+            log.append({"s": round(time.perf_counter() - t0, 3), **_brief(st, th)})
+            print(f"[bench] early-stop {leg} step {k}: {log[-1]}", file=sys.stderr, flush=True)
+        legs[leg] = {"per_step": log,
+                     "avg_relres_y": float(np.mean([r["relres_y"] for r in log])),
+                     "avg_relres_z": float(np.mean([r["relres_z"] for r in log])),
+                     "s_per_step": float(np.mean([r["s"] for r in log]))}
+    rec = {
+        "metric": "true relative residual of budgeted solves (10 epochs per step), "
+                  "warm-started vs cold, early-stopping workload",
+        "value": round(legs["cold"]["avg_relres_z"] / max(legs["warm"]["avg_relres_z"], 1e-30), 4),
+        "unit": "cold / warm average probe residual", "n_gpus": 1, "steps": args.es_steps,
+        "higher_is_better": True, "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": f"early-stopping workload: n={n}, d={w.d}, x~N(0,I), "
+                               f"ell~U[0.3,3], sigma={w.sigma}, s={w.s}, pathwise, "
+                               f"{args.es_solver.upper()} with a budget of {args.es_epochs:g} "
+                               f"epochs" + (f", pivoted-Cholesky rank {args.es_rank}"
+                                            if args.es_solver == "cg" else "") +
+                               ", Adam lr 0.03 from the data-generating theta",
+                   "n": n, "d": w.d, "s": w.s},
+        "legs": legs,
+    }
     print(json.dumps(rec), flush=True)
 
 
@@ -482,6 +559,9 @@ def main():
     if args.init_heuristic:
         init_heuristic(args)
         return
+    if args.early_stop:
+        early_stop(args)
+        return
     import torch
     from paper_2405_18457_amd import api
     torch.cuda.init()
@@ -491,6 +571,20 @@ def main():
     torch.cuda.synchronize()
     n, d, s = inp["n"], inp["w"].d, inp["w"].s
 
+    theta0_info = {"kind": "data-generating theta"}
+    if args.theta0 == "heuristic":
+        import workloads as wl
+        centres = wl.draw_centroids(inp["w"], count=args.init_centres, n=n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th0, _ = api.gp_init_heuristic(ctx, inp["X"], y, centres, args.init_m,
+                                       steps=args.init_steps, lr=0.1)
+        torch.cuda.synchronize()
+        theta0_info = {"kind": "initial-hyperparameter heuristic (App. B)", "s": round(
+            time.perf_counter() - t0, 3), "theta0": [round(float(v), 6) for v in th0],
+            "centres": len(centres), "m": args.init_m, "adam_steps": args.init_steps}
+        print(f"[bench] heuristic theta0 {theta0_info}", file=sys.stderr, flush=True)
+        inp["theta_true"] = th0
     elapsed, log, prof, trainer = run_form(ctx, inp, y, args.form, args.steps, args.warmup,
                                            args.precond_rank, args.precond_reuse)
     value = args.steps / elapsed
@@ -504,11 +598,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"precision workload: n={n}, d={d}, x~U[-1,1]^3, ell~U[0.05,0.2], "
                                f"sigma=0.05, s={s}, pathwise + warm start, CG to rel-res 1e-2, "
-                               "Adam lr 0.03, theta0 = data-generating theta",
+                               "Adam lr 0.03, theta0 = " + (
+                                   "the initial-hyperparameter heuristic" if args.theta0 ==
+                                   "heuristic" else "data-generating theta"),
                    "form": args.form, "n": n, "d": d, "s": s, "solver": "cg", "tol": 1e-2,
                    "precond": (f"pivoted Cholesky rank {args.precond_rank}, factor reused by up to "
                                f"{args.precond_reuse} later steps") if args.precond_rank
                    else "none"},
+        "theta0": theta0_info,
         "per_step": timed,
         "warmup_log": [r for r in log if r["phase"] == "warmup"],
     }

@@ -200,7 +200,9 @@ typedef struct gp_solve_stats {
   int64_t refinements;  /* FP32 true-residual replacements                               */
   double relres_y;      /* ||r_y|| of the normalised system at exit (solver's residual)  */
   double relres_z;      /* mean_j ||r_j|| at exit                                        */
-  double true_relres_y; /* FP32 true residual ||b~ - H u~|| at exit (NaN if not computed)*/
+  double true_relres_y; /* FP32 true residual ||b~ - H u~|| at exit: computed whenever the
+                           budget stops a solve (all solvers) and when CG accepts a
+                           reduced-precision solution; NaN otherwise                    */
   double true_relres_z;
   int converged;        /* 1 if both residual norms reached tol                         */
   int status;           /* gp_status of the solve                                        */

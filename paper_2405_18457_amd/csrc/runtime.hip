@@ -711,6 +711,9 @@ struct OwnStream {
   }
 };
 
+int true_residual_stats(gp_ctx* ctx, const Packed& px, const double* theta, int d, SolveState& s,
+                        gp_solve_stats& stats);
+
 int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
              SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
   const int prec = cfg.precision;
@@ -813,6 +816,9 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
       }
       if (!go || t >= cap) {
         stats.converged = !go;
+        // a solve that the budget stopped reports the FP32 true residual of the
+        // iterate it returns (early stopping, Sec. 5), as AP and SGD do
+        if (go && since_true > 0) CHK(true_residual_stats(ctx, px, theta, d, s, stats));
         break;
       }
     }
@@ -1108,6 +1114,7 @@ void plan_solve(WsPlan& p, int64_t n, int d, int c, const gp_solver_cfg& cfg) {
   plan_kprod(p, n, n, d, c, GP_FP32);  // true residuals
   plan_kprod(p, n, n, d, c, cfg.precision);
   if (cfg.solver == GP_CG) {
+    p.need(B_AUX, vec);  // the true residual of a solve the budget stops
     const int k = (int)std::min<int64_t>(cfg.precond_rank, n);
     if (k > 0) {
       const int64_t ldl = round_up(n, 64);

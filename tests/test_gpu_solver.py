@@ -75,6 +75,10 @@ def test_cg_budget_warm_start_and_scaling(gp):
     assert st["iterations"] == 3 and not st["converged"]
     Uo, so = solvers.cg(op, B, tol=1e-6, max_epochs=3)
     np.testing.assert_allclose(host(U), Uo, rtol=2e-3, atol=2e-4 * np.abs(Uo).max())
+    # a solve the budget stops reports the FP32 true residual of what it returns
+    ry, rz = solvers.true_relres(op, B, host(U))
+    assert st["true_relres_y"] == pytest.approx(ry, rel=1e-3)
+    assert st["true_relres_z"] == pytest.approx(rz, rel=1e-3)
     exact = np.linalg.solve(op.H, B.astype(np.float64)).astype(np.float32)
     U = dev(exact)
     st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-2))
