@@ -96,10 +96,16 @@ def test_trajectory_matches_exact_solves(case, solver):
         cfg = api.solver_cfg(solver=api.GP_SGD, tol=1e-2, sgd_batch=500, sgd_lr=float(lr),
                              sgd_momentum=0.9, sgd_seed=8, max_epochs=200, precision=api.GP_FP32)
     announce("config B trajectory", solver)
+    import time
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     nus, stats = _trajectory(case, cfg, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     dev_per_step = np.max(np.abs(nus - ref), axis=1)
     its = [s["iterations"] for s in stats]
     conv = sum(bool(s["converged"]) for s in stats)
     print(f"[gpu-case] {solver}: max |nu - nu_exact| per step {np.round(dev_per_step, 4).tolist()}; "
-          f"iterations {its}; converged {conv}/{steps}", flush=True)
+          f"iterations {its}; converged {conv}/{steps}; {wall:.1f} s for {steps} steps", flush=True)
     assert float(dev_per_step.max()) <= 0.05
