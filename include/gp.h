@@ -166,12 +166,14 @@ typedef struct gp_solver_cfg {
   int refine_every;     /* FP32 true-residual replacement every k iterations (0 = only
                            at exit); ignored for GP_FP32                                 */
   int check_every;      /* stopping test every k iterations (0 = library default)        */
-  int ap_block;         /* AP block size b (paper: 1000)                                 */
+  int ap_block;         /* AP block size b (paper: 1000), at most 2048                   */
   int sgd_batch;        /* SGD batch size b (paper: 500)                                 */
   double sgd_lr;        /* SGD learning rate gamma                                       */
   double sgd_momentum;  /* SGD momentum rho (paper: 0.9)                                 */
   const int32_t* sgd_batches; /* HOST [sgd_batches_count, sgd_batch] row indices per
-                                 iteration, or NULL to draw them from sgd_seed           */
+                                 iteration, distinct within a batch (an index outside
+                                 [0, n) or repeated in its batch: GP_ERR_INVALID_ARG),
+                                 or NULL to draw them from sgd_seed                      */
   int64_t sgd_batches_count;
   uint64_t sgd_seed;
   int precond_rank;     /* CG only: rank k of the pivoted-Cholesky preconditioner

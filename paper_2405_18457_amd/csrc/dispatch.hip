@@ -131,8 +131,19 @@ __global__ __launch_bounds__(256) void kfwd_reduce(const float* __restrict__ par
   if (idx >= n1 * c) return;
   const int64_t row = idx / c;
   const int col = (int)(idx % c);
+  // the split sums in split order; loads 16 at a time so that many are in flight
   float sum = 0.f;
-  for (int sp = 0; sp < S; ++sp) sum += part[(sp * n1_pad + row) * CP + col];
+  const int64_t stride = n1_pad * CP;
+  const float* p = part + row * CP + col;
+  int sp = 0;
+  for (; sp + 16 <= S; sp += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[(sp + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += v[u];
+  }
+  for (; sp < S; ++sp) sum += p[sp * stride];
   float v = scale * sum;
   if (vn) v = __builtin_fmaf(noise, vn[row * ldv + col], v);
   out[row * ldo + col] = v;

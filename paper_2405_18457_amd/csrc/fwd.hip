@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256, 2) void kfwd_bf16(
 // consecutive floats), and no coordinates are held in registers beyond the NK
 // operands of the lane's rows.  The product's output layout gives each lane rows
 // j = 4g..4g+3 (and 16 + 4g..) of one column i, so the V tiles are packed with the
-// matching row permutation (xt_k_of_j in vec.hip).  The FP32 cancellation error
+// matching row permutation (xt_j_of_k in vec.hip).  The FP32 cancellation error
 // in r^2 grows with |x^|^2; the library uses this path only while the norms stay
 // within the bounds of gpk.h (kXTMaxNorm2 and its companions) and otherwise the
 // direct path.

@@ -216,6 +216,16 @@ hipError_t gather_rows(const float* A, int64_t lda, const int32_t* idx, int64_t 
                        float* out, int64_t ldo, hipStream_t st);
 // G = HI - Bt[idx] (in place in HI); Mom = rho Mom; Mom[idx] -= lr/b G; U += Mom;
 // R[idx] = G (residual estimate).
+// SGD iteration halves (App. B, Algorithm 3): the batch rows' momentum, residual
+// estimate and running column sums of squares (rnorm = their square roots), and
+// the dense momentum decay, U update and packing of U for the next product.
+hipError_t sgd_sparse(const float* G, int64_t ldg, const int32_t* idx, int b, float* Mom,
+                      float* R, int64_t ld, int c, float rho, float lrb, int32_t* stamp, int t,
+                      double* sumsq, double* rnorm, int* status, hipStream_t st);
+hipError_t sgd_update_pack(float* U, float* Mom, int64_t ld, const int32_t* stamp, int t,
+                           float rho, int64_t n, int c, int CT, bool perm, int64_t n_pad,
+                           uint16_t* hi, uint16_t* lo, float* f32, hipStream_t st);
+hipError_t fill_i32(int32_t* dst, int64_t count, int32_t v, hipStream_t st);
 hipError_t sgd_momentum(float* Mom, const float* G, const int32_t* idx, int64_t b, int64_t n,
                         int64_t ld, int c, float rho, float lrb, hipStream_t st);
 hipError_t sgd_finish(float* U, float* R, const float* Mom, const float* G, const int32_t* idx,
@@ -235,7 +245,8 @@ hipError_t check_finite(const float* A, int64_t n, int64_t ld, int c, int* statu
                         hipStream_t st);
 
 // ---------------------------------------------------------------- AP / SGD (solve.hip)
-constexpr int kMaxAPBlock = 2016;  // padded AP block size limit (multiple of 32)
+constexpr int kMaxAPBlock = 2048;  // padded AP block size limit (multiple of 64)
+constexpr int kMaxSolveCP = 256;  // columns of the AP residual update (kMaxSolveC)
 
 // ---------------------------------------------------------------- preconditioner
 // Pivoted-Cholesky construction state (device memory): current pivot, its
@@ -280,12 +291,21 @@ hipError_t ap_cholesky(double* M, int nblk, int P, int* status, hipStream_t st);
 // In-place lower Cholesky of one large P x P matrix (P a multiple of 32) over many
 // workgroups; status bit 2 on a non-positive pivot.
 hipError_t chol_blocked(double* A, int P, int* status, hipStream_t st);
-// out[i, :c] = H[I_blk, I_blk]^-1 R[I_blk, :c] from the cached factor.
+// In place: every block's lower Cholesky factor L becomes L^-1 (lower triangle).
+hipError_t ap_invert_factors(double* M, int nblk, int P, hipStream_t st);
+// out[i, :c] = H[I_blk, I_blk]^-1 R[I_blk, :c] = X^T (X R[I_blk]) with X = L^-1
+// from ap_invert_factors (P a multiple of 64); y: P x c FP64 scratch.
 hipError_t ap_solve_block(const double* M, int P, int blk, int b, int64_t n, const float* R,
-                          int64_t ldr, int c, float* out, int64_t ldo, hipStream_t st);
-// scores[k] = || sum_c R[I_k, c] ||^2
-hipError_t ap_scores(const float* R, int64_t ld, int64_t n, int b, int c, double* scores,
-                     hipStream_t st);
+                          int64_t ldr, int c, double* y, float* out, int64_t ldo, hipStream_t st);
+// Per block k of b rows, split into ap_subblocks(b) equal parts w = k nsub + sub:
+// R[I_k] -= G[I_k] (when G is given; on the rows sel_base .. sel_base + sel_bk
+// also R -= s2 delta), then scores[w] = the part's sum over its rows i of
+// (sum_c R[i, c])^2 (a block's score is the sum over its parts, in order) and
+// part[w * c + col] = the part's sum of R^2.  c <= kMaxSolveCP.
+inline int ap_subblocks(int b) { return (b + 255) / 256; }
+hipError_t ap_update(float* R, int64_t ld, const float* G, int64_t ldg, int64_t n, int b, int c,
+                     int64_t sel_base, int sel_bk, const float* delta, int64_t ldd, float s2,
+                     double* scores, double* part, hipStream_t st);
 // Y[base + i, :] += alpha X[i, :] for i < bk
 hipError_t add_block(float* Y, int64_t ldy, int64_t base, int bk, const float* X, int64_t ldx,
                      int c, float alpha, hipStream_t st);

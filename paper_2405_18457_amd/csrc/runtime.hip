@@ -29,7 +29,7 @@ enum BufId {
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
   B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2,
   B_EXA, B_EXW, B_EXXS, B_EXYS, B_EXDG, B_EXV, B_EXAL, B_EXPART, B_EXGP, B_EXOUT, B_EXIE, B_EXST,
-  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_PCG, B_PCSUM, B_COUNT
+  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_PCG, B_PCSUM, B_STAMP, B_APY, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -277,8 +277,12 @@ int check_prec(gp_ctx* ctx, int prec) {
 }
 
 // ------------------------------------------------------------------ operator
+// With a parent (the packed full set that X's selected rows belong to), the
+// rows inherit its choice of distance form: the rows of a product over a subset
+// are rows of the full product, with the same accuracy, and no norm statistics
+// are read back (no host synchronisation).
 int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64_t n, int d,
-                const double* theta, Packed* p) {
+                const double* theta, Packed* p, const Packed* parent = nullptr) {
   p->n = n;
   p->n_pad = round_up(std::max<int64_t>(n, 1), kRowAlign);
   p->D = select_D(d);
@@ -296,6 +300,12 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
                &p->xt));
   } else {
     p->xt = p->xp;  // the cross-term layout is the packed layout (DP = 4, norm in slot 3)
+  }
+  if (parent) {
+    HIPCHK(pack_x_aug(X, idx, n, d, sc, xt_chunks(p->D), p->xt, p->n_pad, nullptr, ctx->stream));
+    p->xt_ok = parent->xt_ok;
+    p->xt_ok32 = parent->xt_ok32;
+    return GP_OK;
   }
   // squared norms ride in the last slot of the cross-term layout; their maximum and
   // the count above the bulk bound decide whether the cross-term distance form is
@@ -319,13 +329,21 @@ int pack_points(gp_ctx* ctx, BufId id, const float* X, const int32_t* idx, int64
 }
 
 // out[:, :cols] = scale * M(P1, P2) V (+ noise * vn); V has p2.n rows.
+// With v_packed, the forward tiles of V (one pass of at most 80 columns, in the
+// order kprod_v_perm gives) are already in the B_VHI / B_VLO workspace.
+bool kprod_v_perm(const Packed& p1, const Packed& p2, int prec) {
+  return prec == GP_FP32 ? (p1.xt_ok32 && p2.xt_ok32) : (p1.xt_ok && p2.xt_ok);
+}
+
 int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64_t ldv, int cols,
           float* out, int64_t ldo, int prec, float scale, const float* vn, int64_t ldvn,
-          float noise, int fn = FN_MATERN, int fn_dim = 0) {
+          float noise, int fn = FN_MATERN, int fn_dim = 0, bool v_packed = false) {
   // Columns go in balanced passes of at most 80 (5 column tiles with 4 row
   // sub-tiles per wave): wider single passes (8 tiles, 2 sub-tiles) measured
   // slower than two such passes, although each pass re-evaluates the kernel.
   const int npass = (cols + 79) / 80;
+  if (v_packed && (npass != 1 || fn != FN_MATERN))
+    return fail(ctx, GP_ERR_INVALID_ARG, "pre-packed V needs one pass of the kernel product");
   const int per = (cols + npass - 1) / npass;
   for (int c0 = 0; c0 < cols; c0 += per) {
     const int cs = std::min(per, cols - c0);
@@ -348,8 +366,7 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     a.vn = vn ? vn + c0 : nullptr;
     a.ldv = ldvn;
     a.noise = noise;
-    a.xt = fn == FN_MATERN && (prec == GP_FP32 ? (p1.xt_ok32 && p2.xt_ok32)
-                                               : (p1.xt_ok && p2.xt_ok));
+    a.xt = fn == FN_MATERN && kprod_v_perm(p1, p2, prec);
     a.xt1 = p1.xt;
     a.xt2 = p2.xt;
     a.n2_pad = p2.n_pad;
@@ -357,15 +374,17 @@ int kprod(gp_ctx* ctx, const Packed& p1, const Packed& p2, const float* V, int64
     if (prec == GP_FP32) {
       float* vf;
       CHK(ensure(ctx, B_VHI, vcount, &vf));
-      HIPCHK(pack_v_f32(V + c0, p2.n, ldv, cs, nullptr, CT, vf, p2.n_pad, a.xt != 0,
-                        ctx->stream));
+      if (!v_packed)
+        HIPCHK(pack_v_f32(V + c0, p2.n, ldv, cs, nullptr, CT, vf, p2.n_pad, a.xt != 0,
+                          ctx->stream));
       a.vhi = vf;
     } else {
       uint16_t *hi, *lo = nullptr;
       CHK(ensure(ctx, B_VHI, vcount, &hi));
       if (prec == GP_BF16X3) CHK(ensure(ctx, B_VLO, vcount, &lo));
-      HIPCHK(pack_v_bf16(V + c0, p2.n, ldv, cs, nullptr, CT, hi, lo, p2.n_pad, a.xt != 0,
-                         ctx->stream));
+      if (!v_packed)
+        HIPCHK(pack_v_bf16(V + c0, p2.n, ldv, cs, nullptr, CT, hi, lo, p2.n_pad, a.xt != 0,
+                           ctx->stream));
       a.vhi = hi;
       a.vlo = lo;
     }
@@ -897,64 +916,86 @@ int true_residual_stats(gp_ctx* ctx, const Packed& px, const double* theta, int 
   return status_to_error(ctx, st);
 }
 
-// Alternating projections (App. B, Algorithm 2).
+// Alternating projections (App. B, Algorithm 2).  The diagonal blocks H[I, I]
+// are factored once per solve and their Cholesky factors inverted in place, so
+// each iteration's block solve is two triangular products.  An iteration: the
+// block solve for the selected block, u[I] += delta, the column-block product
+// H[:, I] delta, and one pass over R that applies it and yields every block's
+// score and the column norms.
 int ap_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
              SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
   const int64_t n = s.n;
   const int c = s.c;
   const int b = (int)std::min<int64_t>(cfg.ap_block, n);
   if (b < 1) return fail(ctx, GP_ERR_INVALID_ARG, "ap_block must be >= 1");
-  const int P = (int)round_up(b, 32);
+  const int P = (int)round_up(b, 64);
   if (P > kMaxAPBlock)
     return fail(ctx, GP_ERR_INVALID_ARG, "ap_block %d exceeds the supported %d", b, kMaxAPBlock);
   const int nblk = (int)((n + b - 1) / b);
   const double limit = cfg.max_epochs > 0 ? (double)n / b * cfg.max_epochs
                                           : (double)kSafetyCap * nblk;
   const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
-  // Factor every diagonal block once (cached for this solve).
+  // Factor every diagonal block once (cached for this solve) and invert the factors.
   double* M;
   CHK(ensure(ctx, B_APF, (size_t)nblk * P * P, &M));
   HIPCHK(ap_build_blocks(px.xp, px.DP, d, n, b, P, (double)theta[d] * theta[d],
                          (double)theta[d + 1] * theta[d + 1], M, ctx->stream));
   HIPCHK(ap_cholesky(M, nblk, P, s.status, ctx->stream));
+  HIPCHK(ap_invert_factors(M, nblk, P, ctx->stream));
   // r = b~ - H u~ (FP32)
   CHK(true_residual(ctx, px, theta, d, s, GP_FP32, false));
   stats.matvecs += 1;
   float *delta, *G;
+  double *y, *scores;
   CHK(ensure(ctx, B_G, (size_t)P * c, &delta));
+  CHK(ensure(ctx, B_APY, (size_t)P * c, &y));
   CHK(ensure(ctx, B_AUX, (size_t)n * c, &G));
-  double* scores;
-  CHK(ensure(ctx, B_ADJP, (size_t)nblk, &scores));
-  CHK(ensure_pinned(ctx, (size_t)kMaxC + 2 + nblk));
+  // per part of a block: its share of the block's score, then its column sums of squares
+  const int nsub = ap_subblocks(b);
+  const int nparts = nblk * nsub;
+  CHK(ensure(ctx, B_ADJP, (size_t)nparts * (c + 1), &scores));
+  double* part = scores + nparts;
+  CHK(ensure_pinned(ctx, (size_t)kMaxC + 2 + nparts));
+  HIPCHK(ap_update(s.R, c, nullptr, 0, n, b, c, 0, 0, nullptr, 0, 0.f, scores, part,
+                   ctx->stream));
+  HIPCHK(gamma_from_partial(part, nparts, c, nullptr, s.rnorm, s.status, ctx->stream));
   Packed pb;  // the selected block's points as kernel columns
   int64_t t = 0;
   double ry = 0, rz = 0;
   int st = 0;
   Progress prog;
   while (true) {
-    HIPCHK(ap_scores(s.R, c, n, b, c, scores, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->hpin + kMaxC + 2, scores, nblk * sizeof(double),
+    HIPCHK(hipMemcpyAsync(ctx->hpin + kMaxC + 2, scores, nparts * sizeof(double),
                           hipMemcpyDeviceToHost, ctx->stream));
-    CHK(residual_norms(ctx, s, &ry, &rz, &st));
+    CHK(read_norms(ctx, s, &ry, &rz, &st));
     CHK(status_to_error(ctx, st));
     prog.tick("ap", t, ry, rz);
     if (!keep_going(ry, rz, cfg.tol) || !((double)t < limit)) {
       stats.converged = !keep_going(ry, rz, cfg.tol);
       break;
     }
+    // the block with the largest score, the lowest index on ties
     int k = 0;
+    double best = -1.0;
     const double* sc = ctx->hpin + kMaxC + 2;
-    for (int q = 1; q < nblk; ++q)
-      if (sc[q] > sc[k]) k = q;
+    for (int q = 0; q < nblk; ++q) {
+      double v = 0.0;
+      for (int u = 0; u < nsub; ++u) v += sc[q * nsub + u];
+      if (v > best) {
+        best = v;
+        k = q;
+      }
+    }
     const int64_t base = (int64_t)k * b;
     const int bk = (int)std::min<int64_t>(b, n - base);
     // delta = H[I,I]^-1 r[I];  u[I] += delta;  r -= H[:, I] delta
-    HIPCHK(ap_solve_block(M, P, k, b, n, s.R, c, c, delta, c, ctx->stream));
+    HIPCHK(ap_solve_block(M, P, k, b, n, s.R, c, c, y, delta, c, ctx->stream));
     HIPCHK(add_block(s.Ut, c, base, bk, delta, c, c, 1.f, ctx->stream));
-    CHK(pack_points(ctx, B_XP2, X + base * d, nullptr, bk, d, theta, &pb));
+    CHK(pack_points(ctx, B_XP2, X + base * d, nullptr, bk, d, theta, &pb, &px));
     CHK(kprod(ctx, px, pb, delta, c, c, G, c, cfg.precision, a2, nullptr, 0, 0.f));
-    HIPCHK(axpy_cols(s.R, G, n, c, c, -1.f, ctx->stream));
-    HIPCHK(add_block(s.R, c, base, bk, delta, c, c, -s2, ctx->stream));
+    HIPCHK(ap_update(s.R, c, G, c, n, b, c, base, bk, delta, c, s2, scores, part,
+                     ctx->stream));
+    HIPCHK(gamma_from_partial(part, nparts, c, nullptr, s.rnorm, s.status, ctx->stream));
     ++t;
   }
   stats.iterations = t;
@@ -979,7 +1020,15 @@ void draw_batch(std::mt19937_64& rng, int64_t n, int b, int32_t* out, std::vecto
   for (int q = 0; q < cnt; ++q) seen[out[q]] = 0;
 }
 
-// Stochastic gradient descent (App. B, Algorithm 3).
+// Stochastic gradient descent (App. B, Algorithm 3).  An iteration is the row
+// product H[I, :] u on the batch rows (u's forward tiles packed by the previous
+// iteration), the gradient fix-up, ksgd_sparse (batch rows: momentum, residual
+// estimate, running norms) and ksgd_update_pack (all rows: momentum decay,
+// u += m, packing u for the next product).  The residual estimate's column norms
+// are kept as running sums of squares in FP64, recomputed from R every
+// kSgdRenorm iterations.
+constexpr int64_t kSgdRenorm = 1024;
+
 int sgd_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
               SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
   const int64_t n = s.n;
@@ -989,14 +1038,42 @@ int sgd_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta
   double limit = cfg.max_epochs > 0 ? (double)n / b * cfg.max_epochs : (double)kSafetyCap;
   if (cfg.sgd_batches) limit = std::min(limit, (double)cfg.sgd_batches_count);
   const float a2 = a2_of(theta, d), s2 = s2_of(theta, d);
+  const float rho = (float)cfg.sgd_momentum, lrb = (float)(cfg.sgd_lr / b);
   float *Mom, *G;
-  int32_t* idx;
+  int32_t *idx, *stamp;
   CHK(ensure(ctx, B_MOM, (size_t)n * c, &Mom));
   CHK(ensure(ctx, B_G, (size_t)round_up(b, kRowAlign) * c, &G));
   CHK(ensure(ctx, B_IDX, (size_t)b * 2, &idx));
+  CHK(ensure(ctx, B_STAMP, (size_t)n, &stamp));
   HIPCHK(fill(Mom, n * c, 0.f, ctx->stream));
+  HIPCHK(fill_i32(stamp, n, -1, ctx->stream));
   // residual estimate starts at b~ (as printed, also under warm start)
   HIPCHK(copy_cols(s.Bt, c, n, c, s.R, c, ctx->stream));
+  double* sumsq = s.gamma;  // running column sums of squares of R
+  auto renorm = [&]() -> int {
+    HIPCHK(col_dot_partial(s.R, nullptr, n, c, c, c, s.partial, s.nb, ctx->stream));
+    HIPCHK(gamma_from_partial(s.partial, s.nb, c, sumsq, s.rnorm, s.status, ctx->stream));
+    return GP_OK;
+  };
+  CHK(renorm());
+  // forward tiles of u for the product (one pass: c <= 80 columns), packed here
+  // and then by every iteration's update
+  const bool fused = c <= 80;
+  const int CT = select_CT(c);
+  uint16_t *vhi = nullptr, *vlo = nullptr;
+  float* vf = nullptr;
+  const bool perm = kprod_v_perm(px, px, cfg.precision);
+  if (fused) {
+    const size_t vcount = (size_t)(px.n_pad * 16 * CT);
+    if (cfg.precision == GP_FP32) {
+      CHK(ensure(ctx, B_VHI, vcount, &vf));
+      HIPCHK(pack_v_f32(s.Ut, n, c, c, nullptr, CT, vf, px.n_pad, perm, ctx->stream));
+    } else {
+      CHK(ensure(ctx, B_VHI, vcount, &vhi));
+      if (cfg.precision == GP_BF16X3) CHK(ensure(ctx, B_VLO, vcount, &vlo));
+      HIPCHK(pack_v_bf16(s.Ut, n, c, c, nullptr, CT, vhi, vlo, px.n_pad, perm, ctx->stream));
+    }
+  }
   CHK(ensure_pinned(ctx, (size_t)kMaxC + 2 + b));
   int32_t* hidx = reinterpret_cast<int32_t*>(ctx->hpin + kMaxC + 2);
   std::mt19937_64 rng(cfg.sgd_seed);
@@ -1006,7 +1083,8 @@ int sgd_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta
   int st = 0;
   Progress prog;
   while (true) {
-    CHK(residual_norms(ctx, s, &ry, &rz, &st));
+    if (t > 0 && t % kSgdRenorm == 0) CHK(renorm());
+    CHK(read_norms(ctx, s, &ry, &rz, &st));
     CHK(status_to_error(ctx, st));
     prog.tick("sgd", t, ry, rz);
     if (!keep_going(ry, rz, cfg.tol) || !((double)t < limit)) {
@@ -1015,25 +1093,47 @@ int sgd_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta
     }
     if (cfg.sgd_batches) {
       const int32_t* src = cfg.sgd_batches + t * b;
+      if ((int64_t)seen.size() != n) seen.assign(n, 0);
+      int bad = 0;
       for (int q = 0; q < b; ++q) {
-        if (src[q] < 0 || src[q] >= n)
-          return fail(ctx, GP_ERR_INVALID_ARG, "sgd batch index %d out of range", src[q]);
+        if (src[q] < 0 || src[q] >= n) {
+          bad = 1;
+          break;
+        }
+        if (seen[src[q]]) {
+          bad = 2;
+          break;
+        }
+        seen[src[q]] = 1;
         hidx[q] = src[q];
       }
+      for (int q = 0; q < b; ++q)
+        if (src[q] >= 0 && src[q] < n) seen[src[q]] = 0;
+      if (bad == 1) return fail(ctx, GP_ERR_INVALID_ARG, "sgd batch %lld holds an index outside [0, n)", (long long)t);
+      if (bad == 2) return fail(ctx, GP_ERR_INVALID_ARG, "sgd batch %lld repeats an index", (long long)t);
     } else {
       draw_batch(rng, n, b, hidx, seen);
     }
     // the pinned staging buffer is reused next iteration after the norm read syncs
     HIPCHK(hipMemcpyAsync(idx, hidx, b * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     Packed pr;
-    CHK(pack_points(ctx, B_XP2, X, idx, b, d, theta, &pr));
+    CHK(pack_points(ctx, B_XP2, X, idx, b, d, theta, &pr, &px));
     // g[I] = H[I, :] u - b~[I]
-    CHK(kprod(ctx, pr, px, s.Ut, c, c, G, c, cfg.precision, a2, nullptr, 0, 0.f));
+    CHK(kprod(ctx, pr, px, s.Ut, c, c, G, c, cfg.precision, a2, nullptr, 0, 0.f, FN_MATERN, 0,
+              fused));
     HIPCHK(sgd_fix(G, c, s.Ut, s.Bt, c, idx, b, c, s2, ctx->stream));
-    // m = rho m - (gamma/b) g;  u += m;  r[I] = g[I]
-    HIPCHK(sgd_momentum(Mom, G, idx, b, n, c, c, (float)cfg.sgd_momentum,
-                        (float)(cfg.sgd_lr / b), ctx->stream));
-    HIPCHK(sgd_finish(s.Ut, s.R, Mom, G, idx, b, n, c, c, ctx->stream));
+    const int tag = (int)(t & 0x7fffffff);
+    if (fused) {
+      // m[I] = rho m[I] - (lr/b) g; r[I] = g;  m = rho m elsewhere;  u += m
+      HIPCHK(sgd_sparse(G, c, idx, b, Mom, s.R, c, c, rho, lrb, stamp, tag, sumsq, s.rnorm,
+                        s.status, ctx->stream));
+      HIPCHK(sgd_update_pack(s.Ut, Mom, c, stamp, tag, rho, n, c, CT, perm, px.n_pad, vhi, vlo,
+                             vf, ctx->stream));
+    } else {
+      HIPCHK(sgd_momentum(Mom, G, idx, b, n, c, c, rho, lrb, ctx->stream));
+      HIPCHK(sgd_finish(s.Ut, s.R, Mom, G, idx, b, n, c, c, ctx->stream));
+      CHK(renorm());
+    }
     ++t;
   }
   stats.iterations = t;
@@ -1149,18 +1249,20 @@ void plan_solve(WsPlan& p, int64_t n, int d, int c, const gp_solver_cfg& cfg) {
     }
   } else if (cfg.solver == GP_AP) {
     const int b = (int)std::max<int64_t>(1, std::min<int64_t>(cfg.ap_block, n));
-    const int P = (int)round_up(b, 32);
+    const int P = (int)round_up(b, 64);
     const int nblk = (int)((n + b - 1) / b);
     p.need(B_APF, (size_t)nblk * P * P * sizeof(double));
     p.need(B_G, (size_t)P * c * sizeof(float));
+    p.need(B_APY, (size_t)P * c * sizeof(double));
     p.need(B_AUX, vec);
-    p.need(B_ADJP, (size_t)nblk * sizeof(double));
-    p.need_pinned((size_t)kMaxC + 2 + nblk);
+    p.need(B_ADJP, (size_t)nblk * ap_subblocks(b) * (c + 1) * sizeof(double));
+    p.need_pinned((size_t)kMaxC + 2 + (size_t)nblk * ap_subblocks(b));
     plan_pack(p, B_XP2, b, d);  // the selected block's points
     plan_kprod(p, n, b, d, c, cfg.precision);
   } else {
     const int b = (int)std::max<int64_t>(1, std::min<int64_t>(cfg.sgd_batch, n));
     p.need(B_MOM, vec);
+    p.need(B_STAMP, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
     p.need(B_G, (size_t)round_up(b, kRowAlign) * c * sizeof(float));
     p.need(B_IDX, (size_t)b * 2 * sizeof(int32_t));
     p.need(B_AUX, vec);

@@ -68,48 +68,206 @@ __global__ void kpack_x_aug(const float* __restrict__ X, const int32_t* __restri
   }
 }
 
-// Position of row j (within a 32-row tile) on the MFMA contraction index when the
-// kernel tile comes from two 16x16x4 cross-term products (rows 4g..4g+3 and
-// 16+4g..16+4g+3 of lane group g feed k = 8g..8g+7).
-__device__ __forceinline__ int xt_k_of_j(int j) {
-  return 8 * ((j & 15) >> 2) + (j & 3) + 4 * (j >> 4);
+// When the kernel tile comes from two 16x16x4 cross-term products, rows 4g..4g+3
+// and 16+4g..16+4g+3 of a 32-row tile (lane group g) feed positions k = 8g..8g+7
+// of the MFMA contraction index: row j = 16 h + 4 g + r sits at k = 8 g + 4 h + r.
+// This returns the row at position jk.
+__device__ __forceinline__ int xt_j_of_k(int jk) {
+  return 16 * ((jk & 7) >> 2) + 4 * (jk >> 3) + (jk & 3);
 }
 
-__global__ void kpack_v_bf16(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
-                             const float* __restrict__ colscale, int CT,
-                             uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
-                             int64_t n_pad, int perm) {
-  const int CP = 16 * CT;
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= n_pad * CP) return;
-  const int64_t j = t / CP;
-  const int col = (int)(t % CP);
-  float v = 0.f;
-  if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
-  const int jk = perm ? xt_k_of_j((int)(j % 32)) : (int)(j % 32);
-  const int64_t off = ((j / 32) * CT + col / 16) * 512 + (col % 16) * 32 + jk;
-  const uint16_t h = bf16_bits(v);
-  hi[off] = h;
-  if (lo) lo[off] = bf16_bits(v - bf16_val(h));
+constexpr int kPackMaxCP = 128;  // columns of one forward pass (16 * CT, CT <= 8)
+
+// One workgroup per 32-row tile of V: the tile's rows (contiguous for ld == c)
+// are read coalesced into LDS, then its CT blocks of 512 outputs, which are
+// contiguous in the forward layout, are written 16 bytes per thread.
+__device__ void load_v_tile(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
+                            const float* __restrict__ colscale, int CP,
+                            float (*tile)[kPackMaxCP + 1]) {
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  for (int e = threadIdx.x; e < 32 * CP; e += kThreads) {
+    const int r = e / CP, col = e % CP;
+    const int64_t j = j0 + r;
+    float v = 0.f;
+    if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
+    tile[r][col] = v;
+  }
+  __syncthreads();
 }
 
-__global__ void kpack_v_f32(const float* __restrict__ V, int64_t n, int64_t ldv, int c,
-                            const float* __restrict__ colscale, int CT, float* __restrict__ out,
-                            int64_t n_pad, int perm) {
+// bf16 layout: element (row j, column col) at ((j / 32) CT + col / 16) 512 +
+// (col % 16) 32 + jk, jk = j % 32 or its cross-term position.
+__device__ void store_tile_bf16(const float (*tile)[kPackMaxCP + 1], int CT, int perm,
+                                uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  const int64_t base = (int64_t)blockIdx.x * CT * 512;
+  for (int p8 = threadIdx.x; p8 < CT * 64; p8 += kThreads) {
+    const int p = 8 * p8;
+    const int col = 16 * (p >> 9) + ((p & 511) >> 5);
+    const int jk0 = p & 31;
+    uint32_t h2[4], l2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      uint32_t hw = 0, lw = 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int jk = jk0 + 2 * u + q;
+        const float v = tile[perm ? xt_j_of_k(jk) : jk][col];
+        const uint16_t h = bf16_bits(v);
+        const uint16_t l = bf16_bits(v - bf16_val(h));
+        hw |= (uint32_t)h << (16 * q);
+        lw |= (uint32_t)l << (16 * q);
+      }
+      h2[u] = hw;
+      l2[u] = lw;
+    }
+    *reinterpret_cast<uint4*>(hi + base + p) = make_uint4(h2[0], h2[1], h2[2], h2[3]);
+    if (lo) *reinterpret_cast<uint4*>(lo + base + p) = make_uint4(l2[0], l2[1], l2[2], l2[3]);
+  }
+}
+
+// FP32 layout: element (row j, column col) at ((j / 32) CT + col / 16) 512 +
+// ((col % 16) 4 + g) 8 + kk, where lane group g and MFMA step kk consume row
+// jj = j % 32: jj = 4 kk + g (direct kernel) or 16 (kk / 4) + 4 g + kk % 4 (the
+// cross-term output order, see fwd.hip).
+__device__ void store_tile_f32(const float (*tile)[kPackMaxCP + 1], int CT, int perm,
+                               float* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * CT * 512;
+  for (int p4 = threadIdx.x; p4 < CT * 128; p4 += kThreads) {
+    const int p = 4 * p4;
+    const int col = 16 * (p >> 9) + ((p & 511) >> 5);
+    const int g = (p >> 3) & 3;
+    const int kk0 = p & 7;
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = kk0 + u;
+      v[u] = tile[perm ? 16 * (kk >> 2) + 4 * g + (kk & 3) : 4 * kk + g][col];
+    }
+    *reinterpret_cast<float4*>(out + base + p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void kpack_v_bf16(const float* __restrict__ V, int64_t n,
+                                                          int64_t ldv, int c,
+                                                          const float* __restrict__ colscale,
+                                                          int CT, uint16_t* __restrict__ hi,
+                                                          uint16_t* __restrict__ lo, int perm) {
+  __shared__ float tile[32][kPackMaxCP + 1];
+  load_v_tile(V, n, ldv, c, colscale, 16 * CT, tile);
+  store_tile_bf16(tile, CT, perm, hi, lo);
+}
+
+__global__ __launch_bounds__(kThreads) void kpack_v_f32(const float* __restrict__ V, int64_t n,
+                                                         int64_t ldv, int c,
+                                                         const float* __restrict__ colscale,
+                                                         int CT, float* __restrict__ out,
+                                                         int perm) {
+  __shared__ float tile[32][kPackMaxCP + 1];
+  load_v_tile(V, n, ldv, c, colscale, 16 * CT, tile);
+  store_tile_f32(tile, CT, perm, out);
+}
+
+// SGD (App. B, Algorithm 3), the dense half of an iteration, one workgroup per
+// 32-row tile: rows outside this iteration's batch (stamp != t) decay their
+// momentum, Mom = rho Mom (the batch rows were updated by ksgd_sparse); every row
+// moves, U += Mom; the tile of the new U is packed into the forward layout
+// (bf16 hi/lo, or FP32 when f32 is given) for the next iteration's product.
+__global__ __launch_bounds__(kThreads) void ksgd_update_pack(
+    float* __restrict__ U, float* __restrict__ Mom, int64_t ld, const int32_t* __restrict__ stamp,
+    int t, float rho, int64_t n, int c, int CT, int perm, uint16_t* __restrict__ hi,
+    uint16_t* __restrict__ lo, float* __restrict__ f32) {
+  __shared__ float tile[32][kPackMaxCP + 1];
   const int CP = 16 * CT;
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  if (ld == c && j0 + 32 <= n) {
+    // a full tile of contiguous rows: 32 c floats from j0 c (16-byte aligned)
+    for (int e = threadIdx.x; e < 32 * CP; e += kThreads) {
+      const int r = e / CP, col = e % CP;
+      if (col >= c) tile[r][col] = 0.f;
+    }
+    float4* U4 = reinterpret_cast<float4*>(U + j0 * c);
+    float4* M4 = reinterpret_cast<float4*>(Mom + j0 * c);
+    for (int e4 = threadIdx.x; e4 < 8 * c; e4 += kThreads) {
+      float4 m = M4[e4];
+      float4 u = U4[e4];
+      float* mv = reinterpret_cast<float*>(&m);
+      float* uv = reinterpret_cast<float*>(&u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = 4 * e4 + q;
+        const int r = e / c, col = e % c;
+        if (stamp[j0 + r] != t) mv[q] = rho * mv[q];
+        uv[q] = uv[q] + mv[q];
+        tile[r][col] = uv[q];
+      }
+      M4[e4] = m;
+      U4[e4] = u;
+    }
+  } else {
+    for (int e = threadIdx.x; e < 32 * CP; e += kThreads) {
+      const int r = e / CP, col = e % CP;
+      const int64_t j = j0 + r;
+      float v = 0.f;
+      if (j < n && col < c) {
+        const int64_t o = j * ld + col;
+        float m = Mom[o];
+        if (stamp[j] != t) {
+          m = rho * m;
+          Mom[o] = m;
+        }
+        v = U[o] + m;
+        U[o] = v;
+      }
+      tile[r][col] = v;
+    }
+  }
+  __syncthreads();
+  if (f32)
+    store_tile_f32(tile, CT, perm, f32);
+  else
+    store_tile_bf16(tile, CT, perm, hi, lo);
+}
+
+// SGD, the sparse half (one workgroup of 1024 threads): for the batch rows
+// i = idx[q], Mom[i] = rho Mom[i] - (lr / b) G[q] and stamp[i] = t; the residual
+// estimate takes R[i] = G[q], and its running column sums of squares move by
+// G[q]^2 - R_old[i]^2 (lanes in a fixed order, so deterministic); then
+// rnorm = sqrt(sums).  Batch indices are distinct.
+__global__ __launch_bounds__(1024) void ksgd_sparse(
+    const float* __restrict__ G, int64_t ldg, const int32_t* __restrict__ idx, int b,
+    float* __restrict__ Mom, float* __restrict__ R, int64_t ld, int c, float rho, float lrb,
+    int32_t* __restrict__ stamp, int t, double* __restrict__ sumsq, double* __restrict__ rnorm,
+    int* __restrict__ status) {
+  __shared__ double sh[1024];
+  const int lanes = 1024 / c;
+  const int col = threadIdx.x % c, lane = threadIdx.x / c;
+  double acc = 0.0;
+  if (lane < lanes)
+    for (int q = lane; q < b; q += lanes) {
+      const int64_t i = idx[q];
+      const float g = G[(int64_t)q * ldg + col];
+      const int64_t o = i * ld + col;
+      Mom[o] = __builtin_fmaf(-lrb, g, rho * Mom[o]);
+      const float r = R[o];
+      acc += (double)g * g - (double)r * r;
+      R[o] = g;
+      if (col == 0) stamp[i] = t;
+    }
+  sh[threadIdx.x] = lane < lanes ? acc : 0.0;
+  __syncthreads();
+  if (threadIdx.x < c) {
+    double s = 0.0;
+    for (int l = 0; l < lanes; ++l) s += sh[l * c + threadIdx.x];
+    const double v = sumsq[threadIdx.x] + s;
+    sumsq[threadIdx.x] = v;
+    if (!isfinite(v)) atomicOr(status, 1);
+    rnorm[threadIdx.x] = sqrt(v > 0.0 ? v : 0.0);
+  }
+}
+
+__global__ void kfill_i32(int32_t* __restrict__ dst, int64_t count, int32_t v) {
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= n_pad * CP) return;
-  const int64_t j = t / CP;
-  const int col = (int)(t % CP);
-  float v = 0.f;
-  if (j < n && col < c) v = V[j * ldv + col] * (colscale ? colscale[col] : 1.f);
-  const int jj = (int)(j % 32);
-  // lane group g and MFMA step kk that consume row jj of the 32-row tile: row
-  // g + 4 kk (direct kernel) or the cross-term output order (see fwd.hip)
-  const int g = perm ? (jj & 15) >> 2 : jj % 4;
-  const int kk = perm ? (jj & 3) + 4 * (jj >> 4) : jj / 4;
-  const int64_t off = ((j / 32) * CT + col / 16) * 512 + ((col % 16) * 4 + g) * 8 + kk;
-  out[off] = v;
+  if (t < count) dst[t] = v;
 }
 
 __global__ void kpack_rows(const float* __restrict__ U, int64_t n, int64_t ldu, int c,
@@ -160,27 +318,59 @@ __device__ void finish_partial(double v, int c, const ColLanes& cl, double* __re
   }
 }
 
+// The row loops below take kUnroll rows of a lane per step, loads first, then
+// the FP64 sums in row order (so many loads are in flight per wave; the order
+// of the additions is that of the plain loop).
+constexpr int kUnroll = 8;
+
 __global__ void kcol_dot(const float* __restrict__ A, const float* __restrict__ B, int64_t n,
                          int64_t lda, int64_t ldb, int c, double* __restrict__ partial, int nb) {
   const ColLanes cl(c);
   int64_t r0, r1;
   block_rows(n, nb, r0, r1);
   double acc = 0.0;
-  if (cl.active())
-    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+  if (cl.active()) {
+    const int64_t step = cl.lanes;
+    int64_t r = r0 + cl.lane;
+    for (; r + (kUnroll - 1) * step < r1; r += kUnroll * step) {
+      float a[kUnroll], b[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        a[u] = A[(r + u * step) * lda + cl.col];
+        b[u] = B ? B[(r + u * step) * ldb + cl.col] : a[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc += (double)a[u] * (double)b[u];
+    }
+    for (; r < r1; r += step) {
       const double a = A[r * lda + cl.col];
       acc += a * (B ? (double)B[r * ldb + cl.col] : a);
     }
+  }
   finish_partial(acc, c, cl, partial);
+}
+
+// Sum of partial[b * c + col] over b < nb for column col = blockIdx.x, one
+// workgroup per column: thread t adds b = t, t + 256, ... in order, then a fixed
+// tree over the threads (deterministic).  The result is valid in thread 0.
+__device__ double col_total(const double* __restrict__ partial, int nb, int c) {
+  __shared__ double sh[kThreads];
+  const int col = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) s += partial[(int64_t)b * c + col];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
 }
 
 __global__ void kcol_reduce(const double* __restrict__ partial, int nb, int c,
                             double* __restrict__ out) {
-  const int col = threadIdx.x;
-  if (col >= c) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * c + col];
-  out[col] = s;
+  const double s = col_total(partial, nb, c);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 __global__ void knorm_to_scale(const double* __restrict__ sumsq, int c, double eps,
@@ -220,24 +410,41 @@ __global__ void kresidual_init(const float* __restrict__ Bt, const float* __rest
   int64_t r0, r1;
   block_rows(n, nb, r0, r1);
   double acc = 0.0;
-  if (cl.active())
-    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+  if (cl.active()) {
+    const int64_t step = cl.lanes;
+    int64_t r = r0 + cl.lane;
+    for (; r + (kUnroll - 1) * step < r1; r += kUnroll * step) {
+      float v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t o = (r + u * step) * ld + cl.col;
+        v[u] = Bt[o] - HU[o];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t o = (r + u * step) * ld + cl.col;
+        R[o] = v[u];
+        if (set_d) Dv[o] = v[u];
+        acc += (double)v[u] * v[u];
+      }
+    }
+    for (; r < r1; r += step) {
       const int64_t o = r * ld + cl.col;
       const float v = Bt[o] - HU[o];
       R[o] = v;
       if (set_d) Dv[o] = v;
       acc += (double)v * v;
     }
+  }
   finish_partial(acc, c, cl, partial);
 }
 
 __global__ void kcg_alpha(const double* __restrict__ partial, int nb, int c,
                           const double* __restrict__ gamma, double* __restrict__ alpha,
                           int* __restrict__ status) {
-  const int col = threadIdx.x;
-  if (col >= c) return;
-  double dhd = 0.0;
-  for (int b = 0; b < nb; ++b) dhd += partial[(int64_t)b * c + col];
+  const double dhd = col_total(partial, nb, c);
+  const int col = blockIdx.x;
+  if (threadIdx.x != 0) return;
   const bool live = gamma[col] != 0.0;
   double a = 0.0;
   if (live) {
@@ -258,7 +465,25 @@ __global__ void kcg_update_ur(float* __restrict__ U, float* __restrict__ R,
   double acc = 0.0;
   if (cl.active()) {
     const float a = (float)alpha[cl.col];
-    for (int64_t r = r0 + cl.lane; r < r1; r += cl.lanes) {
+    const int64_t step = cl.lanes;
+    int64_t r = r0 + cl.lane;
+    for (; r + (kUnroll - 1) * step < r1; r += kUnroll * step) {
+      float u[kUnroll], rv[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t o = (r + q * step) * ld + cl.col;
+        u[q] = __builtin_fmaf(a, Dv[o], U[o]);
+        rv[q] = __builtin_fmaf(-a, HD[o], R[o]);
+      }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t o = (r + q * step) * ld + cl.col;
+        U[o] = u[q];
+        R[o] = rv[q];
+        acc += (double)rv[q] * rv[q];
+      }
+    }
+    for (; r < r1; r += step) {
       const int64_t o = r * ld + cl.col;
       U[o] = __builtin_fmaf(a, Dv[o], U[o]);
       const float rv = __builtin_fmaf(-a, HD[o], R[o]);
@@ -272,10 +497,9 @@ __global__ void kcg_update_ur(float* __restrict__ U, float* __restrict__ R,
 __global__ void kcg_beta(const double* __restrict__ partial, int nb, int c,
                          double* __restrict__ gamma, double* __restrict__ beta,
                          double* __restrict__ rnorm, int* __restrict__ status) {
-  const int col = threadIdx.x;
-  if (col >= c) return;
-  double g = 0.0;
-  for (int b = 0; b < nb; ++b) g += partial[(int64_t)b * c + col];
+  const double g = col_total(partial, nb, c);
+  const int col = blockIdx.x;
+  if (threadIdx.x != 0) return;
   if (!isfinite(g)) atomicOr(status, 1);
   const double old = gamma[col];
   beta[col] = old != 0.0 ? g / old : 0.0;
@@ -286,10 +510,9 @@ __global__ void kcg_beta(const double* __restrict__ partial, int nb, int c,
 __global__ void kgamma(const double* __restrict__ partial, int nb, int c,
                        double* __restrict__ gamma, double* __restrict__ rnorm,
                        int* __restrict__ status) {
-  const int col = threadIdx.x;
-  if (col >= c) return;
-  double g = 0.0;
-  for (int b = 0; b < nb; ++b) g += partial[(int64_t)b * c + col];
+  const double g = col_total(partial, nb, c);
+  const int col = blockIdx.x;
+  if (threadIdx.x != 0) return;
   if (!isfinite(g)) atomicOr(status, 1);
   if (gamma) gamma[col] = g;
   rnorm[col] = sqrt(g);
@@ -447,15 +670,21 @@ hipError_t pack_x_aug(const float* X, const int32_t* idx, int64_t n, int d, cons
 hipError_t pack_v_bf16(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
                        int CT, uint16_t* hi, uint16_t* lo, int64_t n_pad, bool perm,
                        hipStream_t st) {
-  hipLaunchKernelGGL(kpack_v_bf16, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V,
-                     n, ldv, c, colscale, CT, hi, lo, n_pad, (int)perm);
+  if (CT < 1 || 16 * CT > kPackMaxCP || c > 16 * CT || n_pad % 32 != 0 || n > n_pad)
+    return hipErrorInvalidValue;
+  if (n_pad == 0) return hipSuccess;
+  hipLaunchKernelGGL(kpack_v_bf16, dim3((unsigned)(n_pad / 32)), dim3(kThreads), 0, st, V, n, ldv,
+                     c, colscale, CT, hi, lo, (int)perm);
   return hipGetLastError();
 }
 
 hipError_t pack_v_f32(const float* V, int64_t n, int64_t ldv, int c, const float* colscale,
                       int CT, float* out, int64_t n_pad, bool perm, hipStream_t st) {
-  hipLaunchKernelGGL(kpack_v_f32, dim3(blocks_for(n_pad * 16 * CT)), dim3(kThreads), 0, st, V, n,
-                     ldv, c, colscale, CT, out, n_pad, (int)perm);
+  if (CT < 1 || 16 * CT > kPackMaxCP || c > 16 * CT || n_pad % 32 != 0 || n > n_pad)
+    return hipErrorInvalidValue;
+  if (n_pad == 0) return hipSuccess;
+  hipLaunchKernelGGL(kpack_v_f32, dim3((unsigned)(n_pad / 32)), dim3(kThreads), 0, st, V, n, ldv,
+                     c, colscale, CT, out, (int)perm);
   return hipGetLastError();
 }
 
@@ -488,7 +717,8 @@ hipError_t col_dot_partial(const float* A, const float* B, int64_t n, int64_t ld
 }
 
 hipError_t col_reduce(const double* partial, int nb, int c, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(kcol_reduce, dim3(1), dim3(kThreads), 0, st, partial, nb, c, out);
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kcol_reduce, dim3(c), dim3(kThreads), 0, st, partial, nb, c, out);
   return hipGetLastError();
 }
 
@@ -524,7 +754,8 @@ hipError_t residual_init(const float* Bt, const float* HU, float* R, float* Dv, 
 
 hipError_t cg_alpha(const double* partial, int nb, int c, const double* gamma, double* alpha,
                     int* status, hipStream_t st) {
-  hipLaunchKernelGGL(kcg_alpha, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, alpha,
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kcg_alpha, dim3(c), dim3(kThreads), 0, st, partial, nb, c, gamma, alpha,
                      status);
   return hipGetLastError();
 }
@@ -539,14 +770,16 @@ hipError_t cg_update_ur(float* U, float* R, const float* Dv, const float* HD,
 
 hipError_t cg_beta(const double* partial, int nb, int c, double* gamma, double* beta,
                    double* rnorm, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(kcg_beta, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, beta, rnorm,
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kcg_beta, dim3(c), dim3(kThreads), 0, st, partial, nb, c, gamma, beta, rnorm,
                      status);
   return hipGetLastError();
 }
 
 hipError_t gamma_from_partial(const double* partial, int nb, int c, double* gamma,
                               double* rnorm, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(kgamma, dim3(1), dim3(kThreads), 0, st, partial, nb, c, gamma, rnorm, status);
+  if (c <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kgamma, dim3(c), dim3(kThreads), 0, st, partial, nb, c, gamma, rnorm, status);
   return hipGetLastError();
 }
 
@@ -608,6 +841,33 @@ hipError_t sgd_momentum(float* Mom, const float* G, const int32_t* idx, int64_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return add_rows_scaled(Mom, ld, idx, G, ld, b, c, -lrb, st);
+}
+
+hipError_t sgd_sparse(const float* G, int64_t ldg, const int32_t* idx, int b, float* Mom,
+                      float* R, int64_t ld, int c, float rho, float lrb, int32_t* stamp, int t,
+                      double* sumsq, double* rnorm, int* status, hipStream_t st) {
+  if (c < 1 || c > 256) return hipErrorInvalidValue;
+  if (b <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ksgd_sparse, dim3(1), dim3(1024), 0, st, G, ldg, idx, b, Mom, R, ld, c, rho,
+                     lrb, stamp, t, sumsq, rnorm, status);
+  return hipGetLastError();
+}
+
+hipError_t sgd_update_pack(float* U, float* Mom, int64_t ld, const int32_t* stamp, int t,
+                           float rho, int64_t n, int c, int CT, bool perm, int64_t n_pad,
+                           uint16_t* hi, uint16_t* lo, float* f32, hipStream_t st) {
+  if (CT < 1 || 16 * CT > kPackMaxCP || c > 16 * CT || n_pad % 32 != 0 || n > n_pad)
+    return hipErrorInvalidValue;
+  if (n_pad == 0) return hipSuccess;
+  hipLaunchKernelGGL(ksgd_update_pack, dim3((unsigned)(n_pad / 32)), dim3(kThreads), 0, st, U, Mom,
+                     ld, stamp, t, rho, n, c, CT, (int)perm, hi, lo, f32);
+  return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t* dst, int64_t count, int32_t v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kfill_i32, dim3(blocks_for(count)), dim3(kThreads), 0, st, dst, count, v);
+  return hipGetLastError();
 }
 
 hipError_t sgd_finish(float* U, float* R, const float* Mom, const float* G, const int32_t* idx,

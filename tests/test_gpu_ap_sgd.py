@@ -39,7 +39,8 @@ def test_ap_full_block_is_exact(gp):
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
-@pytest.mark.parametrize("n,b,iters", [(1000, 128, 6), (1337, 200, 9), (700, 700, 1)])
+@pytest.mark.parametrize("n,b,iters", [(1000, 128, 6), (1337, 200, 9), (700, 700, 1),
+                                        (4100, 2000, 3)])
 def test_ap_steps_match_oracle(gp, n, b, iters, prec):
     from paper_2405_18457_amd import api
     import torch
@@ -74,17 +75,20 @@ def test_ap_reaches_tolerance_and_budget(gp):
     assert st["iterations"] == int(np.ceil(n * 1 / 300)) and not st["converged"]
 
 
+# 17 columns: one forward pass, u packed by the fused update; 97 columns: two
+# passes, the unfused update
+@pytest.mark.parametrize("c", [17, 97])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
-def test_sgd_steps_match_oracle(gp, prec):
+def test_sgd_steps_match_oracle(gp, prec, c):
     from paper_2405_18457_amd import api
     import torch
     n, b, iters = 1500, 100, 25
-    X, B, theta = problem(n, 3, 17, seed=42, dist="uniform", sigma=0.3, ell_scale=(0.1, 0.3))
+    X, B, theta = problem(n, 3, c, seed=42, dist="uniform", sigma=0.3, ell_scale=(0.1, 0.3))
     batches = wl.draw_batch_indices(wl.WORKLOADS["B"], iters, b, n=n)
     op = solvers.DenseOperator(X, theta)
     lr = 0.5 * b / np.linalg.eigvalsh(op.H).max()
-    U = torch.zeros((n, 17), device="cuda")
-    announce("sgd-steps", prec)
+    U = torch.zeros((n, c), device="cuda")
+    announce("sgd-steps", prec, c)
     st = api.gp_solve(gp, dev(X), theta, dev(B), U,
                       api.solver_cfg(solver=api.GP_SGD, tol=0.0, sgd_batch=b, sgd_lr=lr,
                                      sgd_momentum=0.9, sgd_batches=batches, precision=prec))
@@ -117,3 +121,21 @@ def test_sgd_budget_and_drawn_batches(gp):
     assert st["converged"]
     ry, rz = solvers.true_relres(op, B, host(U))
     assert max(ry, rz) <= 0.2
+
+
+def test_sgd_rejects_repeated_batch_index(gp):
+    # batch rows must be distinct (the batch's momentum and residual rows are
+    # updated in parallel); the host check rejects the batch before its use
+    from paper_2405_18457_amd import api
+    import torch
+    n, b = 300, 20
+    X, B, theta = problem(n, 3, 5, seed=44, dist="uniform", sigma=0.3, ell_scale=(0.1, 0.3))
+    batches = wl.draw_batch_indices(wl.WORKLOADS["B"], 3, b, n=n)
+    batches[2, 7] = batches[2, 3]
+    U = torch.zeros((n, 5), device="cuda")
+    announce("sgd-repeated-index")
+    with pytest.raises(api.GPError) as e:
+        api.gp_solve(gp, dev(X), theta, dev(B), U,
+                     api.solver_cfg(solver=api.GP_SGD, tol=0.0, sgd_batch=b, sgd_lr=1.0,
+                                    sgd_batches=batches))
+    assert e.value.code == api.N.GP_ERR_INVALID_ARG and "repeats" in str(e.value)
