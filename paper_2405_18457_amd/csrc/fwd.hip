@@ -673,6 +673,172 @@ __global__ __launch_bounds__(256, 2) void kfwd_f32(
                    noise);
 }
 
+// Direct FP32 kernel for wide points (D >= 8): the same arithmetic as kfwd_f32
+// (identical kernel values and MFMA order), but the 32 column points of a step
+// are staged once per workgroup in LDS (three buffers: the current step, the
+// next one, whose sub-tile-0 operand is computed at the end of the current step,
+// and the one being filled) instead of eight points per lane in registers, and
+// two row sub-tiles per wave; at d = 12 that removes the register spills of the
+// register-resident form and leaves LDS for three workgroups per CU.
+template <int D, int FN>
+__device__ __forceinline__ void f32_vals_lds(const float (&xi)[D], const float* xs, int g, int fd,
+                                             float (&m)[8]) {
+  constexpr int DP = (D + 3) & ~3;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) {
+    float xj[D];
+    const float* p = xs + (g + 4 * kk) * DP;
+#pragma unroll
+    for (int q = 0; q < DP / 4; ++q) {
+      const float4 v = *reinterpret_cast<const float4*>(p + 4 * q);
+      if (4 * q + 0 < D) xj[4 * q + 0] = v.x;
+      if (4 * q + 1 < D) xj[4 * q + 1] = v.y;
+      if (4 * q + 2 < D) xj[4 * q + 2] = v.z;
+      if (4 * q + 3 < D) xj[4 * q + 3] = v.w;
+    }
+    m[kk] = (FN == FN_MATERN) ? matern_r2(sqdist<D>(xi, xj)) : dlen_val<D>(xi, xj, fd);
+  }
+}
+
+template <int D, int CT, int FN, int RS>
+__device__ __forceinline__ void f32_step_lds(const float (&xi)[RS][D], const float* xc,
+                                             const float* xn, int g, float (&b)[CT][8],
+                                             const float (&a0)[8], float (&n0)[8],
+                                             f32x4 (&acc)[RS][CT], int fd,
+                                             const float* __restrict__ vnext) {
+  float a[8];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) a[kk] = a0[kk];
+#pragma unroll
+  for (int r = 0; r + 1 < RS; ++r) {
+    float nx[8];
+    f32_vals_lds<D, FN>(xi[r + 1], xc, g, fd, nx);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[r][ct], 0, 0, 0);
+    interleave<8 * CT, 2>();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = nx[kk];
+  }
+  f32_vals_lds<D, FN>(xi[0], xn, g, fd, n0);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+      acc[RS - 1][ct] =
+          __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[ct][kk], acc[RS - 1][ct], 0, 0, 0);
+    const float4 lo4 = *reinterpret_cast<const float4*>(vnext + ct * 512);
+    const float4 hi4 = *reinterpret_cast<const float4*>(vnext + ct * 512 + 4);
+    b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
+    b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
+  }
+  interleave<8 * CT, 2>();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int D, int CT, int FN, int RS>
+__global__ __launch_bounds__(256, 2) void kfwd_f32_lds(
+    const float* __restrict__ xp1, const float* __restrict__ xp2, const float* __restrict__ vf,
+    int64_t n1, int64_t n1_pad, int64_t steps, int S, float* __restrict__ out, int64_t ldo,
+    int c, float* __restrict__ part, float scale, const float* __restrict__ vn, int64_t ldv,
+    float noise, int fn_dim) {
+  constexpr int DP = (D + 3) & ~3;
+  constexpr int NV4 = 8 * DP;                     // float4s of one step's 32 points
+  constexpr int NPF = (NV4 + 255) / 256;          // of them per thread
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int l16 = lane & 15;
+  const int g = lane >> 4;
+  const int64_t rb = blockIdx.x / S;
+  const int64_t sp = blockIdx.x % S;
+  const int64_t row0 = rb * (64 * RS) + wave * (16 * RS);
+  const int64_t s0 = steps * sp / S;
+  const int64_t s1 = steps * (sp + 1) / S;
+
+  float xi[RS][D];
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) load_point<D>(xp1 + (row0 + rs * 16 + l16) * DP, xi[rs]);
+
+  __shared__ float tot_lds[4][RS * CT * 4 * 64];
+  __shared__ __align__(16) float pts[3][32 * DP];
+  float* tl = tot_lds[wave];
+  tot_init<CT, RS>(tl, lane);
+  f32x4 acc[RS][CT];
+  zero<CT, RS>(acc);
+
+  if (s0 < s1) {
+    const int64_t voff = (l16 * 4 + g) * 8;
+    const int64_t tstride = (int64_t)CT * 512;
+    const float4* src = reinterpret_cast<const float4*>(xp2);  // step st: NV4 float4s from st * NV4
+    // steps s0 and s0 + 1 into buffers 0 and 1, step s0 + 2 into the prefetch registers
+    float4 pf[NPF];
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = tid + 256 * u;
+      if (e < NV4) {
+        reinterpret_cast<float4*>(pts[0])[e] = src[s0 * NV4 + e];
+        if (s0 + 1 < s1) reinterpret_cast<float4*>(pts[1])[e] = src[(s0 + 1) * NV4 + e];
+        if (s0 + 2 < s1) pf[u] = src[(s0 + 2) * NV4 + e];
+      }
+    }
+    float b[CT][8];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const float* p = vf + s0 * tstride + voff + ct * 512;
+      const float4 lo4 = *reinterpret_cast<const float4*>(p);
+      const float4 hi4 = *reinterpret_cast<const float4*>(p + 4);
+      b[ct][0] = lo4.x; b[ct][1] = lo4.y; b[ct][2] = lo4.z; b[ct][3] = lo4.w;
+      b[ct][4] = hi4.x; b[ct][5] = hi4.y; b[ct][6] = hi4.z; b[ct][7] = hi4.w;
+    }
+    __syncthreads();
+    float A0[8], A1[8];
+    f32_vals_lds<D, FN>(xi[0], pts[0], g, fn_dim, A0);
+    int64_t st = s0;
+    int cur = 0;
+    int left = kChunk;
+    while (true) {
+      // every wave is done with step st - 1: its buffer takes step st + 2
+      __syncthreads();
+      const int nxt = cur == 2 ? 0 : cur + 1;
+      const int fil = nxt == 2 ? 0 : nxt + 1;
+      if (st + 2 < s1) {
+#pragma unroll
+        for (int u = 0; u < NPF; ++u) {
+          const int e = tid + 256 * u;
+          if (e < NV4) {
+            reinterpret_cast<float4*>(pts[fil])[e] = pf[u];
+            if (st + 3 < s1) pf[u] = src[(st + 3) * NV4 + e];
+          }
+        }
+      }
+      const int64_t nx = st + 1 < s1 ? st + 1 : st;
+      // the last step computes its successor's operand from its own points (unused)
+      const float* xn = st + 1 < s1 ? pts[nxt] : pts[cur];
+      if ((st - s0) & 1)
+        f32_step_lds<D, CT, FN, RS>(xi, pts[cur], xn, g, b, A1, A0, acc, fn_dim,
+                                    vf + nx * tstride + voff);
+      else
+        f32_step_lds<D, CT, FN, RS>(xi, pts[cur], xn, g, b, A0, A1, acc, fn_dim,
+                                    vf + nx * tstride + voff);
+      if (++st >= s1) break;
+      cur = nxt;
+      if (--left == 0) {
+        fold<CT, RS>(tl, acc, lane);
+        left = kChunk;
+      }
+    }
+    fold<CT, RS>(tl, acc, lane);
+  }
+  f32x4 tot[RS][CT];
+  tot_read<CT, RS>(tl, tot, lane);
+  epilogue<CT, RS>(tot, row0, l16, g, n1, n1_pad, c, S, sp, out, ldo, part, scale, vn, ldv,
+                   noise);
+}
+
 // FP32 cross-term kernel: r^2 as in kfwd_bf16_xt, then 8 K=4 FP32 MFMAs per
 // 16-column tile and step with the lane's 8 kernel values as scalar A operands
 // in the order the cross-term output leaves them (k = g of step kk holds column
@@ -862,6 +1028,18 @@ hipError_t launch(const FwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((kfwd_bf16<P_BF16, D, CT, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const uint16_t*)a.vhi, (const uint16_t*)a.vhi, a.n1, a.n1_pad, a.steps,
                        a.S, a.out, a.ldo, a.c, a.part, a.scale, a.vn, a.ldv, a.noise);
+  } else if (D >= 8) {
+    constexpr int RL = 2;
+    if (a.n1_pad % (64 * RL)) return hipErrorInvalidValue;
+    const dim3 gl((unsigned)(a.n1_pad / (64 * RL) * a.S));
+    if (a.fn == FN_MATERN)
+      hipLaunchKernelGGL((kfwd_f32_lds<D, CT, FN_MATERN, RL>), gl, dim3(256), 0, st, a.xp1, a.xp2,
+                         (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,
+                         a.part, a.scale, a.vn, a.ldv, a.noise, a.fn_dim);
+    else
+      hipLaunchKernelGGL((kfwd_f32_lds<D, CT, FN_DLEN, RL>), gl, dim3(256), 0, st, a.xp1, a.xp2,
+                         (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,
+                         a.part, a.scale, a.vn, a.ldv, a.noise, a.fn_dim);
   } else if (a.fn == FN_MATERN) {
     hipLaunchKernelGGL((kfwd_f32<D, CT, FN_MATERN, RS>), grid, dim3(256), 0, st, a.xp1, a.xp2,
                        (const float*)a.vhi, a.n1, a.n1_pad, a.steps, a.S, a.out, a.ldo, a.c,

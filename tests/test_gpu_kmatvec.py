@@ -176,13 +176,15 @@ def test_low_dimension_distance_forms(gp, prec, shift_rows, shift_cols):
     mag_k = kernel.k_matvec(Q, X, theta, np.abs(V)) if prec == 2 else None
     print("[gpu-case] errors", check_product(out, ref, prec, mag_k))
 
-@pytest.mark.parametrize("name,prec", [("B", 0), ("B", 1), ("C", 1), ("E", 1)],
-                         ids=["B-fp32", "B-bf16x3", "C-bf16x3", "E-bf16x3"])
+@pytest.mark.parametrize("name,prec", [("B", 0), ("B", 1), ("C", 1), ("E", 1), ("E", 0)],
+                         ids=["B-fp32", "B-bf16x3", "C-bf16x3", "E-bf16x3", "E-fp32"])
 def test_full_size_workloads_sampled_rows(gp, name, prec):
     """The other workloads at full size and their data-generating hyperparameters
     (B: n = 16,384, d = 24; C: n = 45,730, d = 9; E: n = 2,049,280, d = 11), 65
     columns; sampled output rows against FP64 row products.  At B and E a few
-    points exceed the bulk norm bound of the cross-term form (2 and 474 of them)."""
+    points exceed the bulk norm bound of the cross-term form (2 and 474 of them);
+    their FP32 products take the direct-difference kernel (at E 11,753 points exceed
+    the FP32 bound)."""
     import time
 
     import torch
