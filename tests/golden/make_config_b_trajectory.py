@@ -2,8 +2,9 @@
 optimisation on the 16,384-point workload (d = 24) with the pathwise estimator,
 exact Cholesky solves (the oracle), softplus transform, lr 0.1, theta0 = 1 (the
 paper's small-data settings, App. B "Iterative Optimiser").  Calls only oracle/ and
-the seeded draws of workloads/; the GPU's CG, AP and SGD trajectories are compared
-with it (Sec. 4, Table 1 setting; trajectory bound of 0.05 in nu, half an Adam step).
+the seeded draws of workloads/; the GPU's trajectories are compared with it (Sec. 4,
+Table 1 setting): with tight CG solves every nu within 0.05 (half an Adam step), with
+CG, AP and SGD at tau = 1e-2 the signal and noise scales.
 
 Usage: python tests/golden/make_config_b_trajectory.py [steps]
 """

@@ -156,3 +156,35 @@ def test_cross_term_distances_concentrate_the_error_in_large_norm_rows():
     col, ent = col_relerr(out, ref), elem_relerr(out, ref)
     assert 1e-5 < col <= 2e-5, col
     assert 1.3 * col < ent <= 4e-5, (col, ent)
+
+
+def test_paper_tolerance_solve_moves_small_gradient_components():
+    # Behind the config B trajectory bounds: on the workload's first 4,096 points at
+    # theta0 = 1 (pathwise estimator, its fixed draws), the oracle's own FP64 CG
+    # stopped at tau = 1e-2 gives a gradient within 1e-3 of the exact-solve one in
+    # norm, yet with at least one length-scale component of the opposite sign: that
+    # component is smaller than the error a tau = 1e-2 solve leaves.  Adam's first
+    # step moves each nu by lr times the sign of its component, so trajectories of
+    # such components cannot be held to 0.05 of the exact one at this tolerance,
+    # whatever the solver; the signal and noise scale components are orders of
+    # magnitude above that error.
+    import workloads as wl
+    from oracle import rff, train
+    w = wl.WORKLOADS["B"]
+    n = 4096
+    X = wl.draw_inputs(w, n=n)
+    tr = wl.truth_draws(w, n=n)
+    y = rff.truth_targets_rff(X, tr["ell"], 1.0, w.sigma, tr["t"], tr["w"], tr["noise"])
+    dr = wl.model_pathwise_draws(w, n=n)
+    theta = np.ones(w.d + 2)
+    B = train.build_rhs(X, y.astype(np.float32), theta, "pathwise", dr)
+    Ue, _ = train.solve(X, theta, B, "exact")
+    ge = train.gradient(X, theta, Ue, B, "pathwise")
+    Uc, sc = train.solve(X, theta, B, "cg", tol=1e-2)
+    gc = train.gradient(X, theta, Uc, B, "pathwise")
+    assert sc["converged"]
+    assert np.linalg.norm(gc - ge) / np.linalg.norm(ge) < 1e-3
+    flips = np.nonzero(np.sign(ge[:w.d]) != np.sign(gc[:w.d]))[0]
+    assert len(flips) >= 1, (ge, gc)
+    err = np.abs(gc - ge).max()
+    assert np.all(np.abs(ge[w.d:]) > 100 * err), (ge[w.d:], err)
