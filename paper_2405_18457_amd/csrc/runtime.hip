@@ -760,8 +760,9 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
   int64_t t = 0, since_true = 0;
   double ry = 0, rz = 0;
   double last_true = std::numeric_limits<double>::infinity();
-  // the recurrence's target: tol, lowered after every failed acceptance
+  // the recurrence's target: tol, lowered from the second failed acceptance on
   double tol_in = cfg.tol;
+  int failed = 0;
   int st = 0;
   Progress prog;
   auto cg_iteration = [&]() -> int {
@@ -809,12 +810,13 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
         // The reduced-precision recurrence says converged: accept only on the
         // FP32 true residual.  If it is not yet below tol, restart CG from the
         // true residual (D = R): mixed-precision iterative refinement with CG
-        // as the inner solver, whose target drops by the factor the true
-        // residual overshot tol (between 0.5 and 0.9), since the recurrence
-        // drifts from the true residual again after the restart.  Stop when a
-        // restart lowers the true residual by less than 10 %: the attainable
-        // accuracy of the reduced-precision operator has been reached
-        // (reported as not converged).
+        // as the inner solver.  The first restart keeps the target; from the
+        // second on, the target drops by the factor the true residual
+        // overshot tol (between 0.5 and 0.9), since the recurrence drifts from
+        // the true residual again after a restart, and a restart with a lowered
+        // target that gains less than 10 % on the true residual ends the solve:
+        // the attainable accuracy of the reduced-precision operator has been
+        // reached (reported as not converged).
         CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true, pc));
         stats.matvecs += 1;
         stats.refinements += 1;
@@ -824,14 +826,15 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
         go = keep_going(ry, rz, cfg.tol);
         if (go) {
           const double now = std::max(ry, rz);
-          if (now > 0.9 * last_true) {
+          ++failed;
+          if (failed >= 3 && now > 0.9 * last_true) {
             stats.true_relres_y = ry;
             stats.true_relres_z = rz;
             stats.converged = 0;
             break;
           }
           last_true = now;
-          tol_in *= std::min(0.9, std::max(0.5, cfg.tol / now));
+          if (failed >= 2) tol_in *= std::min(0.9, std::max(0.5, cfg.tol / now));
         }
       }
       if (since_true == 0) {

@@ -40,10 +40,10 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
     operator Hp, stopped when both the mean and the probe relative residual are
     at most tol.  With `mixed`, a recurrence that claims convergence is checked
     on the true residual b - H u (H unperturbed, FP32 rounding) and restarted
-    from it when that is still above tol, with the recurrence's target lowered
-    by the factor tol / (true residual), clamped to [0.5, 0.9]; a restart that
-    lowers the true residual by less than 10 % ends the solve.  Returns
-    (iterations, converged)."""
+    from it when that is still above tol; from the second such restart on the
+    recurrence's target is lowered by the factor tol / (true residual), clamped
+    to [0.5, 0.9], and a restart with a lowered target that gains less than 10 %
+    on the true residual ends the solve.  Returns (iterations, converged)."""
     B64 = np.asarray(B, np.float64)
     scale = 1.0 / (np.sqrt(np.sum(B64 ** 2, axis=0)) + 1e-10)
     Bt = (B64 * scale).astype(np.float32)
@@ -54,6 +54,7 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
     t = since_true = 0
     last_true = np.inf
     tol_in = tol
+    failed = 0
     while True:
         ry, rz = _norms(R)
         if since_true == 0 and t == 0:
@@ -69,10 +70,12 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
             go = ry > tol or rz > tol
             if go:
                 now = max(ry, rz)
-                if now > 0.9 * last_true:
+                failed += 1
+                if failed >= 3 and now > 0.9 * last_true:
                     return t, False
                 last_true = now
-                tol_in *= min(0.9, max(0.5, tol / now))
+                if failed >= 2:
+                    tol_in *= min(0.9, max(0.5, tol / now))
         if not go or t >= max_iter:
             return t, not go
         HD = _f32_product(Hp, D)
