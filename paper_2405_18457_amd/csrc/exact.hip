@@ -463,6 +463,17 @@ hipError_t chol_inv(double* A, double* W, int64_t ld, int64_t off, int64_t m, do
 
 }  // namespace
 
+hipError_t spd_inverse(double* A, double* W, int64_t mp, double* diag, int* status,
+                       hipStream_t st) {
+  if (mp <= 0 || mp % kET) return hipErrorInvalidValue;
+  ExStreams xst{st, nullptr, nullptr, 0, 0};
+  hipError_t e = chol_inv(A, W, mp, 0, mp, diag, status, xst);
+  if (e != hipSuccess) return e;
+  // A^-1 = W^T W into A (lower tiles; op(A) = W^T upper, op(B) = W lower)
+  return gemm(true, false, mp, mp, mp, W, mp, W, mp, A, mp, 1.0, false,
+              kExLowerC | kExAUpper | kExBLower, st);
+}
+
 hipError_t exact_gather(const float* X, int64_t n, int d, const int64_t* idx, int64_t m,
                         int64_t mp, const float* y, double* xs, double* ys, int* status,
                         hipStream_t st) {

@@ -257,7 +257,7 @@ struct PcState {
   int rank;
   double dp;
 };
-constexpr int kMaxPrecondRank = 8192;  // padded rank limit (one inverse column in LDS)
+constexpr int kMaxPrecondRank = 16384;  // rank limit
 int pc_parts(int64_t n);
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
 // One pivoted-Cholesky step j of k (column j for the current pivot, then the next
@@ -273,11 +273,9 @@ hipError_t pc_gram(const float* L, int64_t ldl, int k, int64_t n, double* part,
                    int64_t part_cap, double* G, hipStream_t st);
 hipError_t pc_shift(const double* G, int k, double* A, int kp, double s2, hipStream_t st);
 int64_t pc_gram_parts(int64_t n, int k);
-// M = (C C^T)^-1 for the lower Cholesky factor C (kp x kp, kp <= kMaxPrecondRank,
-// a multiple of 32); W (kp x kp) and part (pc_inverse_parts) are scratch.
-hipError_t pc_inverse(const double* C, int kp, double* W, double* part, int64_t part_cap,
-                      double* M, hipStream_t st);
-int64_t pc_inverse_parts(int kp);
+// M (kp x kp, full) from the lower 64 x 64 tiles of the symmetric A (kp a
+// multiple of 64): M = A^-1 after spd_inverse.
+hipError_t pc_mirror(const double* A, int kp, double* M, hipStream_t st);
 int64_t pc_apply_parts(int64_t n, int k, int c);
 // Z = (R - L M L^T R) / sigma^2 for c columns (T, S: k x c scratch).
 hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
@@ -288,9 +286,6 @@ hipError_t ap_build_blocks(const float* xp, int DP, int d, int64_t n, int b, int
                            double s2, double* M, hipStream_t st);
 // In-place lower Cholesky of nblk P x P blocks; status bit 2 on a non-positive pivot.
 hipError_t ap_cholesky(double* M, int nblk, int P, int* status, hipStream_t st);
-// In-place lower Cholesky of one large P x P matrix (P a multiple of 32) over many
-// workgroups; status bit 2 on a non-positive pivot.
-hipError_t chol_blocked(double* A, int P, int* status, hipStream_t st);
 // In place: every block's lower Cholesky factor L becomes L^-1 (lower triangle).
 hipError_t ap_invert_factors(double* M, int nblk, int P, hipStream_t st);
 // out[i, :c] = H[I_blk, I_blk]^-1 R[I_blk, :c] = X^T (X R[I_blk]) with X = L^-1
@@ -354,6 +349,12 @@ hipError_t exact_finish(const double* xs, const double* ys, int d, int64_t m, in
                         const double* W, const double* diag, double* v, double* alpha,
                         double* part, double* gpart, double* out, hipStream_t st);
 int64_t exact_part_doubles(int64_t mp);
+// In place inverse of an SPD matrix A (mp x mp row-major, mp a multiple of
+// kExactTile, only the lower 64 x 64 tiles read) by the same recursive Cholesky
+// with inverse factor: A^-1 = W^T W is left in the lower tiles of A, W = C^-1 in
+// W, diag[i] = C_ii; status bit 2 on a non-positive pivot.
+hipError_t spd_inverse(double* A, double* W, int64_t mp, double* diag, int* status,
+                       hipStream_t st);
 int64_t exact_gpart_doubles(int64_t mp, int d);
 
 }  // namespace gpk

@@ -333,46 +333,15 @@ __global__ void kpc_sum(const double* __restrict__ part, int nz, int ka, int nb,
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Column a of W = C^-1 for the lower Cholesky factor C (kp x kp, kp a multiple of
-// 32), stored transposed: W[a * kp + i] = (C^-1)[i][a].  Forward substitution on
-// e_a in panels of 32 rows: the rows of a panel first subtract the finished part
-// of the column (coalesced row segments of C, one wave per 8 rows), then wave 0
-// solves the panel's 32 x 32 diagonal block with lane shuffles.  Rows above a's
-// panel stay zero.  M = W^T W is then a product on the matrix cores.
-__global__ __launch_bounds__(256) void kpc_trinv(const double* __restrict__ C, int kp,
-                                                 double* __restrict__ W) {
-  __shared__ double y[kMaxPrecondRank];
-  const int a = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pa = a & ~31;
-  for (int i = tid; i < kp; i += 256) y[i] = (i == a) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int r0 = pa; r0 < kp; r0 += 32) {
-    for (int rr = 0; rr < 8; ++rr) {
-      const int r = r0 + wave * 8 + rr;
-      double acc = 0.0;
-      for (int j = pa + lane; j < r0; j += 64) acc += C[(int64_t)r * kp + j] * y[j];
-      acc = wave_sum(acc);
-      if (lane == 0) y[r] -= acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double v = lane < 32 ? y[r0 + lane] : 0.0;
-      for (int m = 0; m < 32; ++m) {
-        const double ym = __shfl(v, m, 64) / C[(int64_t)(r0 + m) * kp + r0 + m];
-        if (lane == m) v = ym;
-        if (lane > m && lane < 32) v -= C[(int64_t)(r0 + lane) * kp + r0 + m] * ym;
-      }
-      if (lane < 32) y[r0 + lane] = v;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < kp; i += 256) W[(int64_t)a * kp + i] = y[i];
+// M[a][b] = A[max(a, b)][min(a, b)]: the full symmetric matrix from its lower
+// 64 x 64 tiles (the lower tiles hold whole 64 x 64 blocks, both triangles of a
+// diagonal tile included).
+__global__ void kpc_mirror(const double* __restrict__ A, int kp, double* __restrict__ M) {
+  const int64_t t = (int64_t)blockIdx.x * kPcThreads + threadIdx.x;
+  if (t >= (int64_t)kp * kp) return;
+  const int a = (int)(t / kp), b = (int)(t % kp);
+  const bool lower_tile = (a >> 6) >= (b >> 6);
+  M[t] = lower_tile ? A[t] : A[(int64_t)b * kp + a];
 }
 
 // Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2 with L the FP32 factor
@@ -528,29 +497,11 @@ int64_t pc_gram_parts(int64_t n, int k) {
   return ((n + cs - 1) / cs) * (int64_t)k * k;
 }
 
-hipError_t pc_inverse(const double* C, int kp, double* W, double* part, int64_t part_cap,
-                      double* M, hipStream_t st) {
-  if (kp > kMaxPrecondRank || kp % 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kpc_trinv, dim3(kp), dim3(256), 0, st, C, kp, W);
-  // M = W^T W: with W stored transposed, M[a][b] = sum_i W[a][i] W[b][i]
-  const int64_t xt = (kp + 63) / 64;
-  int64_t cs = chunk_rows(kp, xt * xt, 2048);
-  int64_t nz = (kp + cs - 1) / cs;
-  while (nz * (int64_t)kp * kp > part_cap) {
-    cs *= 2;
-    nz = (kp + cs - 1) / cs;
-  }
-  hipLaunchKernelGGL((kpc_tn<4, 1, double>), dim3(xt, xt, nz), dim3(256), 0, st, W, (int64_t)kp,
-                     kp, (int64_t)kp, (const float*)nullptr, (int64_t)0, kp, cs, part);
-  hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, part,
-                     (int)nz, kp, kp, M, kp, 0, 0.0, 0);
+hipError_t pc_mirror(const double* A, int kp, double* M, hipStream_t st) {
+  if (kp <= 0 || kp % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kpc_mirror, dim3(blocks_of((int64_t)kp * kp)), dim3(kPcThreads), 0, st, A, kp,
+                     M);
   return hipGetLastError();
-}
-
-int64_t pc_inverse_parts(int kp) {
-  const int64_t xt = (kp + 63) / 64;
-  const int64_t cs = chunk_rows(kp, xt * xt, 2048);
-  return ((kp + cs - 1) / cs) * (int64_t)kp * kp;
 }
 
 int64_t pc_apply_parts(int64_t n, int k, int c) {

@@ -29,7 +29,7 @@ enum BufId {
   B_WB, B_IDX, B_GX, B_G, B_APF, B_XTMAX, B_Z, B_PCL, B_PCDIAG, B_PCST, B_PCLP, B_PCPV,
   B_PCPI, B_PCPIV, B_PCPART, B_PCA, B_PCM, B_PCT, B_PCS, B_PCELL, B_PCSTAT, B_PCL32, B_PCW, B_POSTD, B_XT1, B_XT2,
   B_EXA, B_EXW, B_EXXS, B_EXYS, B_EXDG, B_EXV, B_EXAL, B_EXPART, B_EXGP, B_EXOUT, B_EXIE, B_EXST,
-  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_PCG, B_PCSUM, B_STAMP, B_APY, B_COUNT
+  B_NRKEY, B_NRST, B_NRCNT, B_NRIDX, B_PCG, B_PCSUM, B_STAMP, B_APY, B_PCID, B_COUNT
 };
 
 constexpr double kNormEps = 1e-10;
@@ -638,22 +638,22 @@ int pc_build(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
     cc.valid = true;
   }
   if (pc.k == 0) return GP_OK;
-  pc.kp = (int)round_up(pc.k, 32);
-  double* A;
+  // M = (sigma^2 I + L^T L)^-1 for this step's sigma: the recursive Cholesky with
+  // inverse factor on the matrix cores (k^3 flops), padded with the identity to a
+  // multiple of 64
+  pc.kp = (int)round_up(pc.k, 64);
+  double *A, *W, *dg;
   int* stat;
   CHK(ensure(ctx, B_PCG, (size_t)pc.k * pc.k, &G));
   CHK(ensure(ctx, B_PCA, (size_t)pc.kp * pc.kp, &A));
+  CHK(ensure(ctx, B_PCW, (size_t)pc.kp * pc.kp, &W));
   CHK(ensure(ctx, B_PCM, (size_t)pc.kp * pc.kp, &pc.M));
+  CHK(ensure(ctx, B_PCID, (size_t)pc.kp, &dg));
   CHK(ensure(ctx, B_PCSTAT, 1, &stat));
   HIPCHK(hipMemsetAsync(stat, 0, sizeof(int), ctx->stream));
   HIPCHK(pc_shift(G, pc.k, A, pc.kp, pc.s2, ctx->stream));
-  HIPCHK(chol_blocked(A, pc.kp, stat, ctx->stream));
-  double* W;
-  CHK(ensure(ctx, B_PCW, (size_t)pc.kp * pc.kp, &W));
-  const int64_t icap = pc_inverse_parts(pc.kp);
-  CHK(ensure(ctx, B_PCPART, (size_t)std::max(icap, pc_gram_parts(n, pc.k)), &part));
-  HIPCHK(pc_inverse(A, pc.kp, W, part, std::max(icap, pc_gram_parts(n, pc.k)), pc.M,
-                    ctx->stream));
+  HIPCHK(spd_inverse(A, W, pc.kp, dg, stat, ctx->stream));
+  HIPCHK(pc_mirror(A, pc.kp, pc.M, ctx->stream));
   int hst = 0;
   HIPCHK(hipMemcpyAsync(ctx->hpin, stat, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1228,7 +1228,7 @@ void plan_solve(WsPlan& p, int64_t n, int d, int c, const gp_solver_cfg& cfg) {
     const int k = (int)std::min<int64_t>(cfg.precond_rank, n);
     if (k > 0) {
       const int64_t ldl = round_up(n, 64);
-      const int kp = (int)round_up(k, 32);
+      const int kp = (int)round_up(k, 64);
       p.need(B_Z, vec);
       p.need(B_PCSUM, sizeof(unsigned long long));
       p.need(B_PCL32, (size_t)k * ldl * sizeof(float));
@@ -1243,8 +1243,9 @@ void plan_solve(WsPlan& p, int64_t n, int d, int c, const gp_solver_cfg& cfg) {
       p.need(B_PCA, (size_t)kp * kp * sizeof(double));
       p.need(B_PCM, (size_t)kp * kp * sizeof(double));
       p.need(B_PCW, (size_t)kp * kp * sizeof(double));
+      p.need(B_PCID, (size_t)kp * sizeof(double));
       p.need(B_PCSTAT, sizeof(int));
-      const int64_t parts = std::max({pc_gram_parts(n, k), pc_inverse_parts(kp),
+      const int64_t parts = std::max({pc_gram_parts(n, k),
                                       pc_apply_parts(n, k, c)});
       p.need(B_PCPART, (size_t)parts * sizeof(double));
       p.need(B_PCT, (size_t)k * c * sizeof(double));

@@ -126,91 +126,6 @@ __global__ __launch_bounds__(256) void kchol(double* __restrict__ M, int P, int*
   if (tid == 0 && bad) atomicOr(status, 2);
 }
 
-// Blocked right-looking Cholesky of one large P x P matrix (P multiple of 32)
-// spread over many workgroups, one 32-column panel at a time: the diagonal tile
-// (one workgroup), the panel below it (one row per thread) and the trailing
-// lower tiles A[it][jt] -= L[it][kt] L[jt][kt]^T (one workgroup per tile).
-__global__ __launch_bounds__(256) void kchol_diag(double* __restrict__ A, int P, int kt,
-                                                  int* status) {
-  __shared__ double Dt[kT][kT + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  const int k0 = kt * kT;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < kT * kT; e += 256) Dt[e / kT][e % kT] = A[(int64_t)(k0 + e / kT) * P + k0 + e % kT];
-  __syncthreads();
-  for (int k = 0; k < kT; ++k) {
-    if (tid == 0) {
-      const double p = Dt[k][k];
-      if (!(p > 0.0)) bad = 1;
-      Dt[k][k] = p > 0.0 ? sqrt(p) : 1.0;
-    }
-    __syncthreads();
-    if (tid > k && tid < kT) Dt[tid][k] /= Dt[k][k];
-    __syncthreads();
-    for (int e = tid; e < kT * kT; e += 256) {
-      const int i = e / kT, j = e % kT;
-      if (j > k && i >= j) Dt[i][j] -= Dt[i][k] * Dt[j][k];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kT * kT; e += 256) {
-    const int i = e / kT, j = e % kT;
-    if (j <= i) A[(int64_t)(k0 + i) * P + k0 + j] = Dt[i][j];
-  }
-  if (tid == 0 && bad) atomicOr(status, 2);
-}
-
-__global__ __launch_bounds__(256) void kchol_panel(double* __restrict__ A, int P, int kt) {
-  __shared__ double Dt[kT][kT + 1];
-  const int tid = threadIdx.x;
-  const int k0 = kt * kT;
-  for (int e = tid; e < kT * kT; e += 256) Dt[e / kT][e % kT] = A[(int64_t)(k0 + e / kT) * P + k0 + e % kT];
-  __syncthreads();
-  const int r = k0 + kT + blockIdx.x * 256 + tid;
-  if (r >= P) return;
-  double x[kT];
-#pragma unroll
-  for (int c = 0; c < kT; ++c) x[c] = A[(int64_t)r * P + k0 + c];
-#pragma unroll
-  for (int c = 0; c < kT; ++c) {
-    double v = x[c];
-#pragma unroll
-    for (int q = 0; q < c; ++q) v -= x[q] * Dt[c][q];
-    x[c] = v / Dt[c][c];
-  }
-#pragma unroll
-  for (int c = 0; c < kT; ++c) A[(int64_t)r * P + k0 + c] = x[c];
-}
-
-// Workgroup b updates the b-th lower tile (it, jt), kt < jt <= it, in row order.
-__global__ __launch_bounds__(256) void kchol_update(double* __restrict__ A, int P, int kt) {
-  __shared__ double Li[kT][kT + 1];
-  __shared__ double Lj[kT][kT + 1];
-  const int tid = threadIdx.x;
-  const int k0 = kt * kT;
-  // tile index b -> (it, jt) with m = it - kt - 1 >= 0 and jt - kt - 1 in [0, m]
-  const int64_t b = blockIdx.x;
-  int m = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(m + 1) * (m + 2) / 2 <= b) ++m;
-  while ((int64_t)m * (m + 1) / 2 > b) --m;
-  const int it = kt + 1 + m;
-  const int jt = kt + 1 + (int)(b - (int64_t)m * (m + 1) / 2);
-  for (int e = tid; e < kT * kT; e += 256) {
-    Li[e / kT][e % kT] = A[(int64_t)(it * kT + e / kT) * P + k0 + e % kT];
-    Lj[e / kT][e % kT] = A[(int64_t)(jt * kT + e / kT) * P + k0 + e % kT];
-  }
-  __syncthreads();
-  for (int e = tid; e < kT * kT; e += 256) {
-    const int i = e / kT, j = e % kT;
-    if (it == jt && j > i) continue;
-    double sacc = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < kT; ++q) sacc += Li[i][q] * Lj[j][q];
-    A[(int64_t)(it * kT + i) * P + jt * kT + j] -= sacc;
-  }
-}
-
 // In place, for every block: the lower Cholesky factor L becomes X = L^-1 (one
 // workgroup per block).  First every 32x32 diagonal tile is inverted (one column
 // of the tile per thread, forward substitution in LDS); then, from X L = I,
@@ -473,21 +388,6 @@ hipError_t ap_build_blocks(const float* xp, int DP, int d, int64_t n, int b, int
   const unsigned gx = (unsigned)std::min<int64_t>((per + 255) / 256, 1024);
   hipLaunchKernelGGL(kbuild_blocks, dim3(gx, nblk), dim3(256), 0, st, xp, DP, d, n, b, P, a2, s2,
                      M);
-  return hipGetLastError();
-}
-
-hipError_t chol_blocked(double* A, int P, int* status, hipStream_t st) {
-  if (P % kT) return hipErrorInvalidValue;
-  const int T = P / kT;
-  for (int kt = 0; kt < T; ++kt) {
-    hipLaunchKernelGGL(kchol_diag, dim3(1), dim3(256), 0, st, A, P, kt, status);
-    const int rows = P - (kt + 1) * kT;
-    if (rows <= 0) break;
-    hipLaunchKernelGGL(kchol_panel, dim3((rows + 255) / 256), dim3(256), 0, st, A, P, kt);
-    const int64_t m = T - kt - 1;
-    hipLaunchKernelGGL(kchol_update, dim3((unsigned)(m * (m + 1) / 2)), dim3(256), 0, st, A, P,
-                       kt);
-  }
   return hipGetLastError();
 }
 
