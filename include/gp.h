@@ -33,6 +33,7 @@
 #ifndef GP_H
 #define GP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -244,7 +245,7 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
  *   piv DEVICE [k] int32 pivot indices (first *rank written)
  *   rank HOST out: the rank reached (<= min(k, n))
  * k = 0 or n = 0 is a no-op with *rank = 0.
- * Errors: GP_ERR_INVALID_ARG (k > 16384, ldl < n, NULL pointers), GP_ERR_HIP. *
+ * Errors: GP_ERR_INVALID_ARG (k > 16384, ldl < n, NULL pointers), GP_ERR_HIP. */
 int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
                         int k, double* L, int64_t ldl, int32_t* piv, int* rank);
 

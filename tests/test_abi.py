@@ -21,6 +21,18 @@ def test_header_declarations_match_binding():
     assert declared_functions() == sorted(N.EXPORTS)
 
 
+@pytest.mark.parametrize("lang,std", [("c", "-std=c11"), ("c++", "-std=c++17")])
+def test_header_compiles_on_its_own(lang, std, tmp_path):
+    # the boundary header is self-contained C11 (and C++): a C caller includes it alone
+    cc = "gcc" if lang == "c" else "g++"
+    src = tmp_path / ("use." + ("c" if lang == "c" else "cpp"))
+    src.write_text('#include "gp.h"\nint main(void) { gp_solver_cfg c; '
+                   'gp_solver_cfg_default(&c); return c.solver; }\n')
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_library_exports_every_declared_symbol():
     assert os.path.exists(N.LIB_PATH), "libgpmi.so not built"
     out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True,
