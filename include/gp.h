@@ -179,7 +179,7 @@ typedef struct gp_solver_cfg {
   uint64_t sgd_seed;
   int precond_rank;     /* CG only: rank k of the pivoted-Cholesky preconditioner
                            P = L L^T + sigma^2 I (App. B uses 100); 0 = none (P = I);
-                           at most 16384 and capped at n                            */
+                           at most 32768 and capped at n                            */
   int use_graph;        /* CG only: run the solve on a library-owned stream (ordered with
                            the context's stream by events) and replay one captured
                            iteration as a HIP graph from the second iteration on; the
@@ -245,7 +245,7 @@ int gp_solve(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
  *   piv DEVICE [k] int32 pivot indices (first *rank written)
  *   rank HOST out: the rank reached (<= min(k, n))
  * k = 0 or n = 0 is a no-op with *rank = 0.
- * Errors: GP_ERR_INVALID_ARG (k > 16384, ldl < n, NULL pointers), GP_ERR_HIP. */
+ * Errors: GP_ERR_INVALID_ARG (k > 32768, ldl < n, NULL pointers), GP_ERR_HIP. */
 int gp_pivoted_cholesky(gp_ctx* ctx, const float* X, int64_t n, int d, const double* theta,
                         int k, double* L, int64_t ldl, int32_t* piv, int* rank);
 

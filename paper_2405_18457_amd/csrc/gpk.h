@@ -257,7 +257,7 @@ struct PcState {
   int rank;
   double dp;
 };
-constexpr int kMaxPrecondRank = 16384;  // rank limit
+constexpr int kMaxPrecondRank = 32768;  // rank limit
 int pc_parts(int64_t n);
 hipError_t pc_init(double* diag, int64_t n, double a2, PcState* s, int32_t* piv, hipStream_t st);
 // One pivoted-Cholesky step j of k (column j for the current pivot, then the next

@@ -41,7 +41,7 @@ def test_pivoted_cholesky_empty_and_invalid(gp):
     L, piv = api.gp_pivoted_cholesky(gp, dev(X), theta, 0)
     assert L.shape[0] == 0 and piv.shape[0] == 0
     with pytest.raises(api.GPError):
-        api.gp_pivoted_cholesky(gp, dev(X), theta, 20000)
+        api.gp_pivoted_cholesky(gp, dev(X), theta, 40000)
 
 
 # The larger case spans many 64-row factor tiles and several row chunks of the
@@ -103,7 +103,7 @@ def test_precond_rank_validation(gp):
     X, B, theta = problem(100, 3, 3, seed=5)
     U = torch.zeros((100, 3), device="cuda")
     with pytest.raises(api.GPError):
-        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(precond_rank=20000))
+        api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(precond_rank=40000))
     with pytest.raises(api.GPError):
         api.gp_solve(gp, dev(X), theta, dev(B), U,
                      api.solver_cfg(solver=api.GP_AP, precond_rank=10, ap_block=50))
