@@ -455,7 +455,8 @@ def _brief(st, theta=None):
             else round(st["relres_y"], 5),
             "relres_z": round(st["true_relres_z"], 5) if st["true_relres_z"] == st["true_relres_z"]
             else round(st["relres_z"], 5),
-            "converged": st["converged"]}
+            "converged": st["converged"],
+            **({"fp32_iters": st["fp32_iterations"]} if st.get("fp32_iterations") else {})}
 
 
 def traffic_per_launch():

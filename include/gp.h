@@ -211,6 +211,9 @@ typedef struct gp_solve_stats {
   int status;           /* gp_status of the solve                                        */
   int precond_rank;     /* rank of the preconditioner actually built (may be below the
                            requested rank when K is numerically of lower rank)          */
+  int64_t fp32_iterations; /* CG only: iterations run with FP32 products after restarts
+                           from the true residual stopped gaining with the requested
+                           reduced precision (0 when that precision reached tol)     */
 } gp_solve_stats;
 
 /* Fill *cfg with the paper's defaults: CG, tol 0.01, no budget, FP32,

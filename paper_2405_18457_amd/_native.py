@@ -50,7 +50,7 @@ class SolveStats(C.Structure):
         ("iterations", C.c_int64), ("epochs", C.c_double), ("matvecs", C.c_int64),
         ("refinements", C.c_int64), ("relres_y", C.c_double), ("relres_z", C.c_double),
         ("true_relres_y", C.c_double), ("true_relres_z", C.c_double), ("converged", C.c_int),
-        ("status", C.c_int), ("precond_rank", C.c_int),
+        ("status", C.c_int), ("precond_rank", C.c_int), ("fp32_iterations", C.c_int64),
     ]
 
     def as_dict(self):

@@ -735,7 +735,9 @@ int true_residual_stats(gp_ctx* ctx, const Packed& px, const double* theta, int 
 
 int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta, int d,
              SolveState& s, const gp_solver_cfg& cfg, gp_solve_stats& stats) {
-  const int prec = cfg.precision;
+  // the products' precision: the requested one, FP32 after an escalation
+  int prec = cfg.precision;
+  bool escalated = false;
   OwnStream own;
   if (cfg.use_graph) CHK(own.enter(ctx));
   Precond pcs;
@@ -811,12 +813,11 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
         // FP32 true residual.  If it is not yet below tol, restart CG from the
         // true residual (D = R): mixed-precision iterative refinement with CG
         // as the inner solver.  The first restart keeps the target; from the
-        // second on, the target drops by the factor the true residual
-        // overshot tol (between 0.5 and 0.9), since the recurrence drifts from
-        // the true residual again after a restart, and a restart with a lowered
-        // target that gains less than 10 % on the true residual ends the solve:
-        // the attainable accuracy of the reduced-precision operator has been
-        // reached (reported as not converged).
+        // second on, the target is halved at every restart (the recurrence
+        // drifts from the true residual again after a restart, and a target just
+        // under tol leaves the restart too little to do), and a restart with a
+        // lowered target that gains less than 10 % on the true residual means
+        // the attainable accuracy of the reduced-precision operator is reached.
         CHK(true_residual(ctx, px, theta, d, s, GP_FP32, true, pc));
         stats.matvecs += 1;
         stats.refinements += 1;
@@ -828,13 +829,29 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
           const double now = std::max(ry, rz);
           ++failed;
           if (failed >= 3 && now > 0.9 * last_true) {
-            stats.true_relres_y = ry;
-            stats.true_relres_z = rz;
-            stats.converged = 0;
-            break;
+            if (!escalated && prec != GP_FP32) {
+              // The reduced-precision operator's attainable accuracy lies above tol:
+              // continue from this true residual (D = R or P^-1 R, just set) with
+              // FP32 products, whose recurrence the true residual then follows.
+              escalated = true;
+              prec = GP_FP32;
+              failed = 0;
+              tol_in = cfg.tol;
+              last_true = now;
+              if (graph_exec) {
+                HIPCHK(hipGraphExecDestroy(graph_exec));
+                graph_exec = nullptr;
+              }
+            } else {
+              stats.true_relres_y = ry;
+              stats.true_relres_z = rz;
+              stats.converged = 0;
+              break;
+            }
+          } else {
+            last_true = now;
+            if (failed >= 2) tol_in *= 0.5;
           }
-          last_true = now;
-          if (failed >= 2) tol_in *= std::min(0.9, std::max(0.5, cfg.tol / now));
         }
       }
       if (since_true == 0) {
@@ -880,6 +897,7 @@ int cg_solve(gp_ctx* ctx, const Packed& px, const float* X, const double* theta,
       CHK(cg_iteration());
     }
     stats.matvecs += 1;
+    if (escalated) stats.fp32_iterations += 1;
     ++t;
     ++since_true;
     if (mixed && cfg.refine_every > 0 && since_true >= cfg.refine_every) {

@@ -41,9 +41,11 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
     at most tol.  With `mixed`, a recurrence that claims convergence is checked
     on the true residual b - H u (H unperturbed, FP32 rounding) and restarted
     from it when that is still above tol; from the second such restart on the
-    recurrence's target is lowered by the factor tol / (true residual), clamped
-    to [0.5, 0.9], and a restart with a lowered target that gains less than 10 %
-    on the true residual ends the solve.  Returns (iterations, converged)."""
+    recurrence's target is halved at every restart, and when a restart with a
+    lowered target gains less than 10 %
+    on the true residual the iteration continues with the unperturbed operator
+    (FP32 products), a second such stall ending the solve.  Returns (iterations,
+    converged, whether the FP32 products took over)."""
     B64 = np.asarray(B, np.float64)
     scale = 1.0 / (np.sqrt(np.sum(B64 ** 2, axis=0)) + 1e-10)
     Bt = (B64 * scale).astype(np.float32)
@@ -55,6 +57,7 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
     last_true = np.inf
     tol_in = tol
     failed = 0
+    escalated = False
     while True:
         ry, rz = _norms(R)
         if since_true == 0 and t == 0:
@@ -72,12 +75,15 @@ def cg_fp32(H, Hp, B, tol, mixed, max_iter=100_000):
                 now = max(ry, rz)
                 failed += 1
                 if failed >= 3 and now > 0.9 * last_true:
-                    return t, False
-                last_true = now
-                if failed >= 2:
-                    tol_in *= min(0.9, max(0.5, tol / now))
+                    if escalated:
+                        return t, False, True
+                    escalated, Hp, failed, tol_in, last_true = True, H, 0, tol, now
+                else:
+                    last_true = now
+                    if failed >= 2:
+                        tol_in *= 0.5
         if not go or t >= max_iter:
-            return t, not go
+            return t, not go, escalated
         HD = _f32_product(Hp, D)
         dhd = np.sum(D.astype(np.float64) * HD.astype(np.float64), axis=0)
         live = gamma > 0

@@ -64,6 +64,37 @@ def test_cg_reaches_tolerance(gp, n, d, c, sigma, prec):
     assert hnorm_err(op.H, Ug, exact) <= 3 * hnorm_err(op.H, Uo, exact) + 1e-4
 
 
+def test_cg_escalates_to_fp32_and_stops_at_its_floor(gp):
+    # tau = 1e-7 lies below what the FP32 true residual itself can resolve on this system
+    # (exact solves with FP32-sized entry errors, 2^-22, leave about 5e-6; the CPU
+    # emulation, tests/test_tolerances.py): the bf16x3 restarts from the true residual
+    # stall, CG continues with FP32 products, those stall too and the solve ends as not
+    # converged, as close to the solution as FP32 allows.  The FP32 form accepts on its
+    # own recurrence (no true-residual check) and never changes precision.
+    from paper_2405_18457_amd import api
+    import torch
+    X, _, theta = problem(600, 3, 1, seed=21, sigma=0.5)
+    g = np.random.default_rng(22)
+    B = np.concatenate([g.standard_normal((600, 1)), g.standard_normal((600, 16))],
+                       axis=1).astype(np.float32)
+    op = solvers.DenseOperator(X, theta)
+    for prec in (api.GP_BF16X3, api.GP_FP32):
+        U = torch.zeros((600, 17), device="cuda")
+        announce("cg-escalation", prec)
+        st = api.gp_solve(gp, dev(X), theta, dev(B), U, api.solver_cfg(tol=1e-7, precision=prec))
+        ry, rz = solvers.true_relres(op, B, host(U))
+        print(f"[gpu-case] escalation {prec}: {st['iterations']} iterations, "
+              f"{st['fp32_iterations']} with FP32 products after a stall, refinements "
+              f"{st['refinements']}, reported {st['true_relres_y']:.2e} / {st['true_relres_z']:.2e}, "
+              f"FP64 residual {ry:.2e} / {rz:.2e}", flush=True)
+        assert max(ry, rz) <= 1e-4
+        if prec == api.GP_BF16X3:
+            assert not st["converged"] and st["fp32_iterations"] > 0
+            assert np.isfinite(st["true_relres_y"]) and np.isfinite(st["true_relres_z"])
+        else:
+            assert st["fp32_iterations"] == 0
+
+
 def test_cg_budget_warm_start_and_scaling(gp):
     from paper_2405_18457_amd import api
     import torch

@@ -188,3 +188,18 @@ def test_paper_tolerance_solve_moves_small_gradient_components():
     assert len(flips) >= 1, (ge, gc)
     err = np.abs(gc - ge).max()
     assert np.all(np.abs(ge[w.d:]) > 100 * err), (ge[w.d:], err)
+
+
+def test_fp32_floor_of_the_escalation_case():
+    # The system of test_cg_escalates_to_fp32_and_stops_at_its_floor (n = 600, d = 3,
+    # sigma = 0.5): exact solves with operators carrying FP32-sized relative entry
+    # errors (2^-22) leave true relative residuals above 1e-6, so tau = 1e-7 is out of
+    # reach of both the bf16x3 and the FP32 products, while 1e-4 is not.
+    from fp32_emulation import attainable_relres
+    from oracle import kernel
+    X, _, theta = problem(600, 3, 1, seed=21, sigma=0.5)
+    g = np.random.default_rng(22)
+    B = np.concatenate([g.standard_normal((600, 1)), g.standard_normal((600, 16))], axis=1)
+    H = kernel.h_matrix(X, theta)
+    floor = attainable_relres(H, B, 2.0 ** -22)
+    assert 1e-6 < floor.min() and floor.max() < 1e-4, floor
