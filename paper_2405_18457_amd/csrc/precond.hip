@@ -12,14 +12,17 @@
 //                  in FP32 (the dot products with earlier columns read half the
 //                  bytes; sums stay FP64); gp_pivoted_cholesky keeps it in FP64.
 //   inverse        M = (sigma^2 I + L^T L)^-1 (k x k, FP64): the Gram matrix on
-//                  FP64 MFMA, a tiled Cholesky (kchol), the triangular inverse
-//                  W = C^-1 by panelled forward substitution (one workgroup per
-//                  column) and M = W^T W on FP64 MFMA.
+//                  FP64 MFMA once per factor; per sigma the shifted matrix,
+//                  padded with the identity to a multiple of 64, goes through
+//                  the recursive matrix-core Cholesky with inverse factor of the
+//                  exact-likelihood code (spd_inverse), and kpc_mirror fills in
+//                  the upper triangle.
 //   apply          P^-1 R = (R - L (M (L^T R))) / sigma^2 (Woodbury), the skinny
 //                  products and M (L^T R) LDS-tiled on FP64 MFMA with FP64
-//                  accumulation; the
-//                  subtraction cancels most of R, which is why the arithmetic
-//                  is FP64.  The products read an FP32 copy of the factor (the
+//                  accumulation (with 65 columns the last one runs on the vector
+//                  ALU beside the 64 matrix-core columns); the subtraction
+//                  cancels most of R, which is why the arithmetic is FP64.  The
+//                  products read an FP32 copy of the factor (the
 //                  preconditioner is P = L~ L~^T + sigma^2 I for that copy L~,
 //                  Gram matrix included, so P stays exactly SPD).
 //
@@ -232,15 +235,17 @@ __device__ __forceinline__ void load_seg(const T* __restrict__ L, int rows, int6
     v[e] = (a < rows && i + e < iend) ? L[(int64_t)a * ldl + i + e] : T(0);
 }
 
-template <int NBT, int BMODE, typename TL, typename TR = float, int WPE = 4>
+template <int NBT, int BMODE, typename TL, typename TR = float, int WPE = 4, bool X1 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void kpc_tn(const TL* __restrict__ L, int64_t ldl, int ka,
                                               int64_t n, const TR* __restrict__ R,
                                               int64_t ldr, int nb, int64_t csize,
                                               double* __restrict__ part) {
-  constexpr int NB = 16 * NBT;
+  constexpr int NB = 16 * NBT;            // columns on the matrix cores
+  constexpr int NBX = NB + (X1 ? 1 : 0);  // columns of the B tile
   static_assert(BMODE == 0 || NB == 64, "the factor-operand loader covers 64 columns");
+  static_assert(!X1 || BMODE == 0, "the extra column is a column of R");
   __shared__ double As[64][kTI + 1];
-  __shared__ double Bs[kTI][NB + 1];
+  __shared__ double Bs[kTI][NBX + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int la = lane & 15, lk = lane >> 4;
@@ -251,24 +256,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double xacc = 0.0;  // X1: the extra column b0 + NB on the vector ALU
   // loaders: the factor tile with 4 threads per 32-value row segment (8 values
-  // each); BMODE 0 with 8 threads per row of the B tile, NB / 8 consecutive
-  // columns each; BMODE 1 like the factor tile.  The next stage is fetched into
-  // registers while the MFMAs of the current one run.
+  // each); BMODE 0 reads the kTI x NBX B tile as consecutive entries, BPT per
+  // thread (entry f = 256 e + tid: row f / NBX, column f % NBX), so that the
+  // lanes of a wave load consecutive addresses of a row; BMODE 1 like the
+  // factor tile.  The next stage is fetched into registers while the MFMAs of
+  // the current one run.
   const int lr = tid >> 2, lc = (tid & 3) * 8;
-  constexpr int BPT = NB / 8;
-  const int br = tid >> 3, bc = (tid & 7) * BPT;
+  constexpr int BT = kTI * NBX;
+  constexpr int BPT = (BT + 255) / 256;
   TL ra[8];
   TR rb[BMODE == 0 ? BPT : 1];
   TL rl[8];
   auto fetch = [&](int64_t i) {
     load_seg(L, ka, ldl, a0 + lr, i + lc, i1, ra);
     if constexpr (BMODE == 0) {
-      const int64_t ii = i + br;
 #pragma unroll
       for (int e = 0; e < BPT; ++e) {
-        const int bcol = b0 + bc + e;
-        rb[e] = (ii < i1 && bcol < nb) ? R[ii * ldr + bcol] : TR(0);
+        const int f = 256 * e + tid;
+        const int64_t ii = i + f / NBX;
+        const int bcol = b0 + f % NBX;
+        rb[e] = (f < BT && ii < i1 && bcol < nb) ? R[ii * ldr + bcol] : TR(0);
       }
     } else {
       load_seg(L, nb, ldl, b0 + lr, i + lc, i1, rl);
@@ -280,7 +289,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
     for (int e = 0; e < 8; ++e) As[lr][lc + e] = (double)ra[e];
     if constexpr (BMODE == 0) {
 #pragma unroll
-      for (int e = 0; e < BPT; ++e) Bs[br][bc + e] = (double)rb[e];
+      for (int e = 0; e < BPT; ++e) {
+        const int f = 256 * e + tid;
+        if (f < BT) Bs[f / NBX][f % NBX] = (double)rb[e];
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) Bs[lc + e][lr] = (double)rl[e];
@@ -294,6 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       for (int u = 0; u < NBT; ++u)
         acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[4 * s4 + lk][16 * u + la], acc[u], 0,
                                                       0, 0);
+      if constexpr (X1) xacc = fma(av, Bs[4 * s4 + lk][NB], xacc);
     }
     __syncthreads();
   }
@@ -305,6 +318,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       const int bc = b0 + 16 * u + la;
       if (ar < ka && bc < nb) part[((int64_t)blockIdx.z * ka + ar) * nb + bc] = acc[u][q];
     }
+  if constexpr (X1) {
+    // the four lane groups hold the sums over i = 4s + 0..3: add them pairwise
+    xacc += __shfl_xor(xacc, 16);
+    xacc += __shfl_xor(xacc, 32);
+    const int ar = a0 + 16 * wave + la;
+    if (lk == 0 && ar < ka && b0 + NB < nb)
+      part[((int64_t)blockIdx.z * ka + ar) * nb + b0 + NB] = xacc;
+  }
 }
 
 // out[a][b] = sum_z part[z][a][b] (fixed order).  With diag_add: out is the
@@ -349,14 +370,15 @@ __global__ void kpc_mirror(const double* __restrict__ A, int kp, double* __restr
 // are staged in LDS as FP64 (A lane: L[t + 4s + l/16][i0 + 16w + l%16]; B lane:
 // S[t + 4s + l/16][c0 + 16u + l%16]; D lane q: (i0 + 16w + 4q + l/16,
 // c0 + 16u + l%16)).
-template <int NBT>
+template <int NBT, bool X1 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kpc_apply(const float* __restrict__ L, int64_t ldl, int k,
                                                  int64_t n, const double* __restrict__ S, int nb,
                                                  const float* __restrict__ R, int64_t ldr,
                                                  float* __restrict__ Z, int64_t ldz, double s2) {
-  constexpr int NB = 16 * NBT;
+  constexpr int NB = 16 * NBT;            // columns on the matrix cores
+  constexpr int NBX = NB + (X1 ? 1 : 0);  // columns of the S tile
   __shared__ double As[kTI][64 + 1];
-  __shared__ double Bs[kTI][NB + 1];
+  __shared__ double Bs[kTI][NBX + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int la = lane & 15, lk = lane >> 4;
@@ -365,21 +387,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   f64x4 acc[NBT];
 #pragma unroll
   for (int u = 0; u < NBT; ++u) acc[u] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // loaders: 8 threads per 64-value row segment of the factor (8 values each) and
-  // 8 threads per row of the S tile (NB / 8 columns each); the next stage is
-  // fetched into registers while the MFMAs of the current one run.
+  double xacc = 0.0;  // X1: the extra column c0 + NB on the vector ALU
+  // loaders: 8 threads per 64-value row segment of the factor (8 values each);
+  // the kTI x NBX tile of S as consecutive entries, BPT per thread (entry
+  // f = 256 e + tid: row f / NBX, column f % NBX); the next stage is fetched
+  // into registers while the MFMAs of the current one run.
   const int lr = tid >> 3, lc = (tid & 7) * 8;
-  constexpr int BPT = NB / 8;
-  const int bc = (tid & 7) * BPT;
+  constexpr int BT = kTI * NBX;
+  constexpr int BPT = (BT + 255) / 256;
   float ra[8];
   double rb[BPT];
   auto fetch = [&](int t0) {
     load_seg(L, k, ldl, t0 + lr, i0 + lc, n, ra);
-    const int t = t0 + lr;
 #pragma unroll
     for (int e = 0; e < BPT; ++e) {
-      const int col = c0 + bc + e;
-      rb[e] = (t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
+      const int f = 256 * e + tid;
+      const int t = t0 + f / NBX;
+      const int col = c0 + f % NBX;
+      rb[e] = (f < BT && t < k && col < nb) ? S[(int64_t)t * nb + col] : 0.0;
     }
   };
   if (k > 0) fetch(0);
@@ -387,7 +412,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int e = 0; e < 8; ++e) As[lr][lc + e] = (double)ra[e];
 #pragma unroll
-    for (int e = 0; e < BPT; ++e) Bs[lr][bc + e] = rb[e];
+    for (int e = 0; e < BPT; ++e) {
+      const int f = 256 * e + tid;
+      if (f < BT) Bs[f / NBX][f % NBX] = rb[e];
+    }
     __syncthreads();
     if (t0 + kTI < k) fetch(t0 + kTI);
 #pragma unroll
@@ -397,6 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int u = 0; u < NBT; ++u)
         acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[4 * s4 + lk][16 * u + la], acc[u], 0,
                                                       0, 0);
+      if constexpr (X1) xacc = fma(av, Bs[4 * s4 + lk][NB], xacc);
     }
     __syncthreads();
   }
@@ -409,6 +438,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int c = c0 + 16 * u + la;
       if (i < n && c < nb) Z[i * ldz + c] = (float)(((double)R[i * ldr + c] - acc[u][q]) * inv);
     }
+  if constexpr (X1) {
+    // the four lane groups hold the sums over t = 4s + 0..3: add them pairwise
+    xacc += __shfl_xor(xacc, 16);
+    xacc += __shfl_xor(xacc, 32);
+    const int64_t i = i0 + 16 * wave + la;
+    const int c = c0 + NB;
+    if (lk == 0 && i < n && c < nb) Z[i * ldz + c] = (float)(((double)R[i * ldr + c] - xacc) * inv);
+  }
 }
 
 // FP32 copy of the factor (rows >= n of each factor column set to zero).
@@ -504,34 +541,84 @@ hipError_t pc_mirror(const double* A, int kp, double* M, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Chunk count for the skinny products of the apply.  Every workgroup does the
+// same work, so among nz0 .. 2 nz0 chunks (nz0 = max(1, 2048 / tiles)) the
+// count whose workgroups fill the last round of the CUs' concurrent slots
+// (CUs x workgroups per CU) best is taken; ties go to the smaller count.
+static int64_t apply_nz0(int64_t tiles) {
+  const int64_t nz0 = 2048 / (tiles > 0 ? tiles : 1);
+  return nz0 < 1 ? 1 : nz0;
+}
+
+static int64_t balanced_nz(int64_t tiles, int per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  const int64_t slots = (int64_t)cus * per_cu, nz0 = apply_nz0(tiles);
+  int64_t best = nz0;
+  double best_fill = 0.0;
+  for (int64_t nz = nz0; nz <= 2 * nz0; ++nz) {
+    const int64_t wg = tiles * nz;
+    const double fill = (double)wg / (double)(((wg + slots - 1) / slots) * slots);
+    if (fill > best_fill) {
+      best_fill = fill;
+      best = nz;
+    }
+  }
+  return best;
+}
+
+// Rows per chunk for nz chunks of n rows (a multiple of 16, at least 64).
+static int64_t rows_per_chunk(int64_t n, int64_t nz) {
+  int64_t cs = (n + nz - 1) / nz;
+  cs = (cs + 15) / 16 * 16;
+  return cs < 64 ? 64 : cs;
+}
+
+// 65 columns (64 probe vectors and the mean column): 64 on the matrix cores and
+// one on the vector ALU in the same pass over the factor, instead of 80 padded
+// matrix-core columns.
+constexpr int kApplyX1Cols = 65;
+
 int64_t pc_apply_parts(int64_t n, int k, int c) {
-  const int64_t tiles = (k + 63) / 64 * ((c + 79) / 80);
-  const int64_t cs = chunk_rows(n, tiles, 2048), cs2 = chunk_rows(k, tiles, 2048);
+  // the chunk count grows with the requested count, which is at most 2 nz0
+  const int64_t tiles = (k + 63) / 64 * ((c + 79) / 80), nzmax = 2 * apply_nz0(tiles);
+  const int64_t cs = rows_per_chunk(n, nzmax), cs2 = rows_per_chunk(k, nzmax);
   const int64_t nz1 = (n + cs - 1) / cs, nz2 = (k + cs2 - 1) / cs2;
-  const int64_t nz = nz1 > nz2 ? nz1 : nz2;
-  return nz * (int64_t)k * c;
+  return (nz1 > nz2 ? nz1 : nz2) * (int64_t)k * c;
 }
 
 hipError_t pc_apply(const float* L, int64_t ldl, int k, int64_t n, const double* M, int kp,
                     const float* R, int64_t ldr, int c, double* part, double* T, double* S,
                     float* Z, int64_t ldz, double s2, hipStream_t st) {
   if (k > 0 && n > 0) {
+    // workgroups per CU: 4 for the FP32-factor product (LDS and its register
+    // target), 3 for the all-FP64 one (registers)
     const int64_t xt = (k + 63) / 64, yt = (c + 79) / 80;
-    const int64_t cs = chunk_rows(n, xt * yt, 2048);
+    const int64_t cs = rows_per_chunk(n, balanced_nz(xt * yt, 4));
     const int64_t nz = (n + cs - 1) / cs;
-    hipLaunchKernelGGL((kpc_tn<5, 0, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R, ldr,
-                       c, cs, part);
+    if (c == kApplyX1Cols)
+      hipLaunchKernelGGL((kpc_tn<4, 0, float, float, 4, true>), dim3(xt, 1, nz), dim3(256), 0, st, L,
+                         ldl, k, n, R, ldr, c, cs, part);
+    else
+      hipLaunchKernelGGL((kpc_tn<5, 0, float>), dim3(xt, yt, nz), dim3(256), 0, st, L, ldl, k, n, R,
+                         ldr, c, cs, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz, k, c, T, c, 0, 0.0, 0);
     // S = M T (k x c, reduction over the k factor columns) on the same tiled product
-    const int64_t cs2 = chunk_rows(k, xt * yt, 2048);
+    const int64_t cs2 = rows_per_chunk(k, balanced_nz(xt * yt, 3));
     const int64_t nz2 = (k + cs2 - 1) / cs2;
     hipLaunchKernelGGL((kpc_tn<5, 0, double, double, 3>), dim3(xt, yt, nz2), dim3(256), 0, st, M,
                        (int64_t)kp, k, (int64_t)k, T, (int64_t)c, c, cs2, part);
     hipLaunchKernelGGL(kpc_sum, dim3(blocks_of((int64_t)k * c)), dim3(kPcThreads), 0, st, part,
                        (int)nz2, k, c, S, c, 0, 0.0, 0);
   }
-  if (n > 0)
+  if (n > 0 && c == kApplyX1Cols)
+    hipLaunchKernelGGL((kpc_apply<4, true>), dim3((n + 63) / 64, 1), dim3(256), 0, st, L, ldl, k, n,
+                       S, c, R, ldr, Z, ldz, s2);
+  else if (n > 0)
     hipLaunchKernelGGL((kpc_apply<5>), dim3((n + 63) / 64, (c + 79) / 80), dim3(256), 0, st, L,
                        ldl, k, n, S, c, R, ldr, Z, ldz, s2);
   return hipGetLastError();

@@ -52,19 +52,24 @@ def test_pivoted_cholesky_empty_and_invalid(gp):
 # perturbation eps of every kernel entry moves the oracle's own U by about
 # 218 eps of max|U| there (3.6 eps in the smaller case).  bf16x3 drops terms of
 # relative size 2^-16 per entry, hence 218 * 2^-16 = 3.3e-3, bounded by 5e-3.
+# With 65 columns (64 probes and the mean column, the column count whose
+# preconditioner apply runs the 65th column on the vector ALU) the sensitivity is
+# 1.15x (4000 rows) and 1.4x (900 rows) that of the 9-column cases, which the
+# same bounds still cover.
 ATOL_FRAC = {(900, 0): 2e-4, (900, 1): 2e-4, (4000, 0): 2e-4, (4000, 1): 5e-3}
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16x3"])
-@pytest.mark.parametrize("n,k,seed", [(900, 60, 31), (4000, 1000, 57)])
-def test_pcg_steps_match_oracle_under_a_budget(gp, prec, n, k, seed):
+@pytest.mark.parametrize("n,k,seed,c", [(900, 60, 31, 9), (900, 60, 31, 65), (4000, 1000, 57, 9),
+                                        (4000, 1000, 57, 65)])
+def test_pcg_steps_match_oracle_under_a_budget(gp, prec, n, k, seed, c):
     from paper_2405_18457_amd import api
     import torch
-    X, B, theta = problem(n, 3, 9, seed=seed, dist="uniform", sigma=0.05, ell_scale=(0.2, 0.5))
+    X, B, theta = problem(n, 3, c, seed=seed, dist="uniform", sigma=0.05, ell_scale=(0.2, 0.5))
     op = solvers.DenseOperator(X, theta)
     P = precond.preconditioner(X, theta, k)
-    announce("pcg-budget", prec, n, k)
-    U = torch.zeros((n, 9), device="cuda")
+    announce("pcg-budget", prec, n, k, c)
+    U = torch.zeros((n, c), device="cuda")
     st = api.gp_solve(gp, dev(X), theta, dev(B), U,
                       api.solver_cfg(tol=1e-8, max_epochs=4, precision=prec, precond_rank=k))
     assert st["iterations"] == 4 and not st["converged"] and st["precond_rank"] == k
