@@ -53,9 +53,10 @@ def test_pivoted_cholesky_empty_and_invalid(gp):
 # 218 eps of max|U| there (3.6 eps in the smaller case).  bf16x3 drops terms of
 # relative size 2^-16 per entry, hence 218 * 2^-16 = 3.3e-3, bounded by 5e-3.
 # With 65 columns (64 probes and the mean column, the column count whose
-# preconditioner apply runs the 65th column on the vector ALU) the sensitivity is
-# 1.15x (4000 rows) and 1.4x (900 rows) that of the 9-column cases, which the
-# same bounds still cover.
+# preconditioner apply runs the 65th column on the vector ALU) a 2^-16 error per
+# entry moves the oracle's U by 8.1e-5 (900 rows) and 3.6e-3 (4000 rows) of
+# max|U|, against 5.6e-5 and 3.3e-3 with 9 columns (tests/test_tolerances.py),
+# inside the same bounds.
 ATOL_FRAC = {(900, 0): 2e-4, (900, 1): 2e-4, (4000, 0): 2e-4, (4000, 1): 5e-3}
 
 
