@@ -209,11 +209,14 @@ __global__ __launch_bounds__(kPcThreads) void kpc_pivot(const double* __restrict
 // LDS as FP64 and every wave runs v_mfma_f64_16x16x4f64 on 16 a-rows x NBT
 // column tiles (A lane: L[a0 + 16w + l%16][i + 4s + l/16]; B lane:
 // Bop(i + 4s + l/16, b0 + 16u + l%16); D lane q: (a0 + 16w + 4q + l/16,
-// b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.  WPE is the
-// occupancy the register allocation aims for (4 waves per SIMD is also the LDS
-// limit; the all-FP64 instantiation needs 3 to stay clear of spills).
+// b0 + 16u + l%16)).  Products of two FP32 values are exact in FP64.  X1 adds
+// the column b0 + 16*NBT on the vector ALU: each lane accumulates its A value
+// times that column's entry in FP64, and the four lane groups (l/16) are summed
+// at the end.  WPE is the occupancy the register allocation aims for (4 waves
+// per SIMD is also the LDS limit; the all-FP64 instantiation needs 3 to stay
+// clear of spills).
 constexpr int kTI = 32;  // rows i per LDS stage
-static_assert(kTI * 8 == 256, "B-tile loaders map 8 threads to each of the kTI rows");
+static_assert(kTI * 8 == 256, "the factor-tile loaders cover kTI with 4 or 8 threads of 8 values");
 
 // Eight consecutive entries [i, i + 8) of row a of a [rows][ldl] operand, zero
 // past iend or the row count; two 16-byte loads when the segment is whole (FP32
@@ -366,8 +369,9 @@ __global__ void kpc_mirror(const double* __restrict__ A, int kp, double* __restr
 }
 
 // Z[i][c] = (R[i][c] - sum_t L[t][i] S[t][c]) / sigma^2 with L the FP32 factor
-// copy.  One workgroup: 64 rows i x 16*NBT columns; tiles of 32 factor columns t
-// are staged in LDS as FP64 (A lane: L[t + 4s + l/16][i0 + 16w + l%16]; B lane:
+// copy.  One workgroup: 64 rows i x 16*NBT columns (plus column c0 + 16*NBT on
+// the vector ALU with X1, as in kpc_tn); tiles of 32 factor columns t are staged
+// in LDS as FP64 (A lane: L[t + 4s + l/16][i0 + 16w + l%16]; B lane:
 // S[t + 4s + l/16][c0 + 16u + l%16]; D lane q: (i0 + 16w + 4q + l/16,
 // c0 + 16u + l%16)).
 template <int NBT, bool X1 = false>
